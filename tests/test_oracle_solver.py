@@ -1,0 +1,173 @@
+"""Pins for the oracle's solver (Algorithm 4), degree rule (Algorithm 3) and bounds.
+
+* config-1 eigenvalues against the closed-form 2D Laplacian spectrum;
+* n <= 2000 versions of the other workloads against dense eigendecomposition;
+* scripted Ritz sequences for the spurious-value / locking control (Section 3.3.2);
+* Algorithm 3's recurrence against direct trigonometric evaluation of the series.
+"""
+import numpy as np
+import pytest
+
+from oracle import bounds, closed_form
+from oracle import coefficients as co
+from oracle import solver
+from oracle.degree import select_degree
+from workloads import (
+    build_config,
+    laplacian_3d_dirichlet,
+    random_banded_symmetric,
+    start_block,
+    tight_binding_3d_periodic,
+)
+
+
+def _window(w, lo_idx, count):
+    """Interval holding eigenvalues w[lo_idx : lo_idx+count], endpoints mid-gap."""
+    a = 0.5 * (w[lo_idx - 1] + w[lo_idx])
+    b = 0.5 * (w[lo_idx + count - 1] + w[lo_idx + count])
+    return a, b
+
+
+def test_config1_matches_closed_form():
+    A, (lmin, lmax), (a, b), cfg = build_config("lap2d_64")
+    exact = closed_form.lap2d_eigs(64)
+    exact = exact[(exact >= a) & (exact <= b)]
+    assert exact.size == 40
+    X0 = start_block(A.n, cfg.p, seed=0)
+    r = solver.solve(A, a, b, lmin, lmax, X0, solver.Options(kmax=cfg.degree))
+    normA = max(abs(lmin), abs(lmax))
+    assert r.converged
+    assert r.eigenvalues.size == 40
+    assert np.max(np.abs(r.eigenvalues - exact)) <= 1e-10 * normA
+    assert np.max(r.residuals) <= 1e-9 * normA
+    # recomputed residuals of the returned vectors
+    D = A.to_scipy()
+    R = D @ r.eigenvectors - r.eigenvectors * r.eigenvalues
+    assert np.max(np.linalg.norm(R, axis=0)) <= 1e-9 * normA
+    G = r.eigenvectors.T @ r.eigenvectors
+    assert np.max(np.abs(G - np.eye(40))) < 1e-12
+
+
+def _brute_force_case(A, count, p, degree, seed, adaptive=False, damping="jackson"):
+    D = A.to_dense()
+    w = np.linalg.eigvalsh(D)
+    lo_idx = A.n // 2 - count // 2
+    a, b = _window(w, lo_idx, count)
+    lmin, lmax = w[0] - 1e-2, w[-1] + 1e-2
+    X0 = start_block(A.n, p, seed=seed, complex_=np.iscomplexobj(A.val))
+    opts = solver.Options(kmax=degree, adaptive=adaptive, damping=damping, max_iter=400)
+    r = solver.solve(A, a, b, lmin, lmax, X0, opts)
+    normA = max(abs(lmin), abs(lmax))
+    assert r.converged
+    assert r.eigenvalues.size == count
+    assert np.max(np.abs(r.eigenvalues - w[lo_idx: lo_idx + count])) <= 1e-10 * normA
+    assert np.max(r.residuals) <= 1e-9 * normA
+    return r
+
+
+def test_brute_force_lap3d_potential_12():
+    _brute_force_case(laplacian_3d_dirichlet(12, potential_scale=2.0, seed=1), 16, 48, 200, 0)
+
+
+def test_brute_force_tight_binding_12():
+    _brute_force_case(tight_binding_3d_periodic(12, seed=1), 16, 48, 200, 1)
+
+
+def test_brute_force_random_banded_2000():
+    _brute_force_case(random_banded_symmetric(2000, seed=1, band=16), 12, 48, 200, 2)
+
+
+def test_brute_force_adaptive_lanczos():
+    r = _brute_force_case(laplacian_3d_dirichlet(12, potential_scale=2.0, seed=3), 16, 32, 300, 0,
+                          adaptive=True, damping="lanczos")
+    assert min(r.degrees) < 300
+
+
+# ------------------------------------------------------------ control logic (fake backend)
+
+def test_control_spurious_values_do_not_block_termination():
+    # Ritz values inside [0, 1]: three true pairs converging, two spurious pairs with
+    # residual 1e-1 near the ends (the pattern of Section 3.3.2)
+    a, b = 0.0, 1.0
+    ritz = np.array([-0.5, 0.04, 0.3, 0.5, 0.7, 0.96, 1.4])
+    I = np.array([1, 2, 3, 4, 5])
+    state = solver.ControlState()
+    seq = [1e-2, 1e-4, 1e-6, 1e-8, 1e-11]
+    done_at = None
+    for it, r in enumerate(seq):
+        res = np.array([1e-1, r, r, r, 1e-1])
+        I_fin, L, done = solver.control_step(ritz, res, I, a, b, 1e-10, state)
+        if it == 0:
+            # tau_s = 0.04; C = three true pairs; n_check 3 != previous 0 -> I unchanged
+            assert list(I_fin) == [1, 2, 3, 4, 5]
+        else:
+            assert list(I_fin) == [2, 3, 4]
+        if done:
+            done_at = it
+            assert list(L) == [2, 3, 4]
+            break
+    assert done_at == 4
+
+
+def test_control_without_stable_count_keeps_spurious():
+    a, b = 0.0, 1.0
+    ritz = np.array([0.04, 0.5, 0.96])
+    state = solver.ControlState()
+    # n_check changes every iteration (1 then 2) -> I is never replaced
+    I_fin, L, done = solver.control_step(ritz, np.array([1e-1, 1e-3, 1e-1]), np.arange(3), a, b, 1e-10, state)
+    assert list(I_fin) == [0, 1, 2] and not done
+    I_fin, L, done = solver.control_step(ritz, np.array([1e-1, 1e-12, 1e-3]), np.arange(3), a, b, 1e-10, state)
+    assert list(I_fin) == [0, 1, 2] and list(L) == [1] and not done
+
+
+def test_control_counts_locked_pairs_in_n_check():
+    a, b = 0.0, 1.0
+    state = solver.ControlState(n_lock=2, n_check_prev=3)
+    ritz = np.array([0.5, 0.98])
+    I_fin, L, done = solver.control_step(ritz, np.array([1e-12, 0.5]), np.arange(2), a, b, 1e-10, state)
+    # C = {0}, n_check = 1 + 2 = 3 equals previous -> I = C -> locked, done
+    assert list(I_fin) == [0] and list(L) == [0] and done
+
+
+# ------------------------------------------------------------ Algorithm 3
+
+@pytest.mark.parametrize("damping", ["lanczos", "jackson"])
+def test_select_degree_against_trig_form(damping):
+    lmin, lmax = -1.0, 3.0
+    a, b = 0.9, 1.1
+    k = 150
+    c = co.filter_coefficients(lmin, lmax, a, b, k, damping, 0.5)
+    l1, l2 = co.affine_map(lmin, lmax)
+    rng = np.random.default_rng(0)
+    for trial in range(6):
+        e = 3 + trial
+        inside = rng.uniform(a + 0.01, b - 0.01, size=e)
+        outside = np.concatenate([rng.uniform(lmin, a - 0.15 - 0.05 * trial, size=5),
+                                  rng.uniform(b + 0.15 + 0.05 * trial, lmax, size=5)])
+        ritz = np.sort(np.concatenate([inside, outside]))
+        got = select_degree(ritz, e, c, l1, l2, 1e-3)
+        # brute force: first j whose truncated series meets the test
+        expect = k
+        for j in range(1, k + 1):
+            g = np.sort(np.abs(co.filter_value(ritz, c, lmin, lmax, degree=j)))[::-1]
+            if g[e - 1] != 0 and g[ritz.size - 1] / g[e - 1] < 1e-3:
+                expect = j
+                break
+        assert got == expect
+
+
+def test_select_degree_returns_max_when_never_met():
+    c = co.filter_coefficients(-1, 1, -0.1, 0.1, 20, "jackson")
+    ritz = np.array([-0.05, 0.0, 0.05])  # every Ritz value inside: ratio is never small
+    assert select_degree(ritz, 3, c, 1.0, 0.0, 1e-3) == 20
+
+
+# ------------------------------------------------------------ spectral bounds
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_lanczos_bounds_enclose_spectrum(cplx):
+    A = tight_binding_3d_periodic(8, seed=4) if cplx else laplacian_3d_dirichlet(8, 2.0, seed=4)
+    w = np.linalg.eigvalsh(A.to_dense())
+    lo, hi = bounds.lanczos_bounds(A, steps=60)
+    assert lo <= w[0] and hi >= w[-1]
+    assert hi - lo < 1.2 * (w[-1] - w[0])

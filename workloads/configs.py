@@ -1,0 +1,127 @@
+"""The synthetic workloads: matrix recipe, spectral bounds, interval, block width, degree.
+
+Sizes follow the five workloads the build is measured on:
+
+1. 2D 5-point Dirichlet Laplacian 64x64 (n = 4096), window holding exactly 40
+   eigenvalues (#38..#77 of the closed-form spectrum), p = 64, degree 60, Jackson, FP64.
+2. 3D 7-point Dirichlet Laplacian 100^3 (n = 1e6) + 2*U(0,1) diagonal potential,
+   mid-spectrum window, p = 256, degree 120, Jackson, FP64 and FP32 filter.
+3. Complex tight-binding 64^3 periodic lattice (n = 262144), window around 0,
+   p = 192, degree 150, Jackson, complex FP64 and complex FP32 filter.
+4. Random irregular symmetric n = 2e6, ~24 nnz/row, central window,
+   p = 640, degree 200, Jackson, FP32 filter with FP64 projections.
+5. Serving stream (see :mod:`workloads.stream`).
+
+Spectral bounds are the closed form for config 1 and Gershgorin discs otherwise.
+``scale`` shrinks a workload for tests (grid edge or n); the recipe stays the same.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Callable
+
+import numpy as np
+
+from .matrices import (
+    CSR,
+    gershgorin_bounds,
+    laplacian_2d_dirichlet,
+    laplacian_3d_dirichlet,
+    random_banded_symmetric,
+    tight_binding_3d_periodic,
+)
+
+
+@dataclass
+class WorkloadConfig:
+    name: str
+    description: str
+    make_matrix: Callable[[int, int], CSR]  # (size, seed) -> CSR
+    size: int                               # grid edge or n at full scale
+    p: int
+    degree: int
+    damping: str
+    complex_: bool
+    filter_dtypes: tuple
+    interval: Callable[[float, float], tuple]  # (lo, hi) -> (a, b)
+    exact_bounds: Callable[[int], tuple] | None = None
+    extra: dict = field(default_factory=dict)
+
+
+def _centred(width: float):
+    def f(lo, hi):
+        c = 0.5 * (lo + hi)
+        return (c - 0.5 * width, c + 0.5 * width)
+
+    return f
+
+
+def _lap2d_bounds(N):
+    c = np.cos(np.pi / (N + 1))
+    return (4.0 - 4.0 * c, 4.0 + 4.0 * c)
+
+
+CONFIGS = {
+    "lap2d_64": WorkloadConfig(
+        name="lap2d_64",
+        description="2D 5-point Dirichlet Laplacian 64x64, n=4096, 40-eigenvalue window",
+        make_matrix=lambda size, seed: laplacian_2d_dirichlet(size),
+        size=64,
+        p=64,
+        degree=60,
+        damping="jackson",
+        complex_=False,
+        filter_dtypes=("f64",),
+        interval=lambda lo, hi: (0.128538339316, 0.255551112680),
+        exact_bounds=_lap2d_bounds,
+    ),
+    "lap3d_pot_100": WorkloadConfig(
+        name="lap3d_pot_100",
+        description="3D 7-point Dirichlet Laplacian 100^3 + 2*U(0,1) potential, n=1e6",
+        make_matrix=lambda size, seed: laplacian_3d_dirichlet(size, potential_scale=2.0, seed=seed),
+        size=100,
+        p=256,
+        degree=120,
+        damping="jackson",
+        complex_=False,
+        filter_dtypes=("f64", "f32"),
+        interval=_centred(1.39e-3),
+    ),
+    "tb3d_64": WorkloadConfig(
+        name="tb3d_64",
+        description="complex tight-binding 64^3 periodic, random bond phases, n=262144",
+        make_matrix=lambda size, seed: tight_binding_3d_periodic(size, seed=seed),
+        size=64,
+        p=192,
+        degree=150,
+        damping="jackson",
+        complex_=True,
+        filter_dtypes=("c128", "c64"),
+        interval=_centred(4.85e-3),
+    ),
+    "rand_2m": WorkloadConfig(
+        name="rand_2m",
+        description="random irregular symmetric n=2e6, half banded (+-64) half random columns",
+        make_matrix=lambda size, seed: random_banded_symmetric(size, seed=seed),
+        size=2_000_000,
+        p=640,
+        degree=200,
+        damping="jackson",
+        complex_=False,
+        filter_dtypes=("f32", "f64"),
+        interval=_centred(4.0e-3),
+    ),
+}
+
+
+def build_config(name: str, size: int | None = None, seed: int = 0):
+    """Return (A, (lo, hi), (a, b), cfg) for a named workload, optionally resized."""
+    cfg = CONFIGS[name]
+    size = cfg.size if size is None else size
+    A = cfg.make_matrix(size, seed)
+    if cfg.exact_bounds is not None:
+        lo, hi = cfg.exact_bounds(size)
+    else:
+        lo, hi = gershgorin_bounds(A)
+    a, b = cfg.interval(lo, hi)
+    return A, (lo, hi), (a, b), cfg
