@@ -1,0 +1,292 @@
+#!/usr/bin/env python3
+"""Benchmark: filtered subspace iteration on one MI355X.
+
+One step = one iteration of the solver on the 3D Laplacian + potential workload
+(n = 100^3, p = 256, Jackson degree 120): the Clenshaw filter (120 fused sparse x
+block products), CholQR2 orthonormalisation, Rayleigh-Ritz, residual norms and
+the locking test.  Inputs are resident on the GPU before timing starts.
+
+value = algorithmic filter bytes moved per step / wall time per step (GB/s),
+i.e. the filter's throughput with the rest of the iteration counted as overhead.
+The roofline object reports the steady-state Clenshaw kernel alone, timed with
+HIP events on the stream it runs on.  cpu_baseline times the oracle's filter on
+a bounded sample of the same workload on the host cores.
+
+Usage: python bench.py [--steps K] [--warmup W] [--form fp64|mixed] [--gpus 1]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def filter_bytes(nnz, n, p, sx, sval, coeffs, degree):
+    """Algorithmic (compulsory) bytes of one filter application and of one steady launch.
+
+    Per product: the CSR matrix once (values, int32 columns, int32 row pointers) plus
+    one pass over each dense block it touches: the gathered source once, the block
+    b_{j+2} read in place, X when its coefficient is nonzero, and the output write.
+    """
+    a_bytes = nnz * (sval + 4) + 4 * (n + 1)
+    pb = n * p * sx
+    total = 0
+    for s in range(degree):
+        j = degree - 1 - s
+        if s == 0:
+            passes = 2                                   # read X, write b_{k-1}
+        elif s == 1:
+            passes = 2 + (1 if coeffs[j] - coeffs[degree] != 0 else 0)
+        else:
+            passes = 3 + (1 if coeffs[j] != 0 else 0)    # src, V in place, write (+ X)
+        total += a_bytes + passes * pb
+    steady = a_bytes + 4 * pb
+    return total, steady
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--form", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--workload", default="lap3d_pot_100")
+    ap.add_argument("--size", type=int, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--cpu-sample-steps", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(see the sharding notes in DESIGN.md); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2604_00914_amd import afsi
+    from paper_2604_00914_amd import build as hipbuild
+    from workloads import build_config, start_block
+
+    if not os.path.exists(afsi.LIB_PATH):
+        hipbuild.build()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    t0 = time.time()
+    A, (lmin, lmax), (a, b), cfg = build_config(args.workload, size=args.size, seed=0)
+    n, p, k = A.n, cfg.p, cfg.degree
+    cplx = A.is_complex
+    log(f"workload {cfg.name}: n={n} nnz={A.nnz} p={p} k={k} bounds=({lmin:.4g},{lmax:.4g}) "
+        f"interval=({a:.6g},{b:.6g}) gen {time.time() - t0:.1f}s")
+    M = afsi.Matrix(A, device=0, bounds=(lmin, lmax))
+    coeffs = afsi.afsi_filter_coefficients(lmin, lmax, a, b, k, cfg.damping)
+    X0 = start_block(n, p, seed=0, complex_=cplx)
+    f64 = torch.complex128 if cplx else torch.float64
+    f32 = torch.complex64 if cplx else torch.float32
+    fdt = f64 if args.form == "fp64" else f32
+    B0 = torch.from_numpy(X0).to(dev)
+    del X0
+    B1, B2 = torch.empty_like(B0), torch.empty_like(B0)
+    if args.form == "mixed":
+        F0 = torch.empty((n, p), dtype=f32, device=dev)
+        F1, F2 = torch.empty_like(F0), torch.empty_like(F0)
+    stream = torch.cuda.current_stream()
+    afsi.afsi_orthonormalize(None, B0, B1)
+    torch.cuda.synchronize()
+
+    sx = {torch.float64: 8, torch.float32: 4, torch.complex128: 16, torch.complex64: 8}[fdt]
+    sval = sx  # the matrix values are read in the filter's precision
+    fbytes, steady_bytes = filter_bytes(A.nnz, n, p, sx, sval, coeffs, k)
+
+    def run_filter(deg):
+        if args.form == "fp64":
+            afsi.afsi_filter_block(M.handle, coeffs, deg, B0, B1, B2)
+        else:
+            afsi.afsi_convert_block(B0, F0)
+            afsi.afsi_filter_block(M.handle, coeffs, deg, F0, F1, F2)
+            afsi.afsi_convert_block(F1, B1)
+
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    filt_ms = []
+    n_check = [0]
+
+    def step():
+        nonlocal B0, B1, B2
+        ev[0].record(stream)
+        run_filter(k)
+        ev[1].record(stream)
+        afsi.afsi_orthonormalize(None, B1, B2)
+        ritz = afsi.afsi_rayleigh_ritz(M.handle, B1, B0, B2)
+        res = afsi.afsi_residual_norms(B0, B2, ritz)
+        inside = (ritz >= a) & (ritz <= b)
+        if inside.any():
+            normA = max(abs(lmin), abs(lmax))
+            _, _, _, n_check[0] = afsi.afsi_lock_select(ritz, res, inside, a, b, 1e-10 * normA, 0, n_check[0])
+        filt_ms.append(ev[0].elapsed_time(ev[1]))
+
+    # degree-2 filters time the first two (special) products, so that the
+    # steady-state kernel's per-launch time is (t_k - t_2) / (k - 2)
+    t2 = []
+    for w in range(max(args.warmup, 1)):
+        step()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        for _ in range(3):
+            e0.record(stream)
+            run_filter(2)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            t2.append(e0.elapsed_time(e1))
+    filt_ms.clear()
+    torch.cuda.synchronize()
+    log(f"warmup done; timing {args.steps} steps")
+    tstart = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - tstart
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = fbytes * args.steps / elapsed / 1e9
+    t2_med = float(np.median(t2))
+    filt_med = float(np.median(filt_ms))
+    steady_launch_ms = (filt_med - t2_med) / (k - 2)
+    achieved = steady_bytes / (steady_launch_ms * 1e-3) / 1e9
+    filter_gbs = fbytes / (filt_med * 1e-3) / 1e9
+    log(f"step {ms_per_step:.2f} ms, filter {filt_med:.2f} ms ({filter_gbs:.0f} GB/s), "
+        f"steady launch {steady_launch_ms * 1e3:.1f} us ({achieved:.0f} GB/s)")
+
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", f"traffic_{cfg.name}_{args.form}.json")
+    if os.path.exists(tpath):
+        traffic = json.load(open(tpath)).get("hbm_bytes_per_launch")
+
+    out = {
+        "metric": "SpMM-filter GB/s (% HBM peak); eigenpairs/s mixed vs FP64; p99 latency",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "c128" if cplx else "f64", "mixed": "c64" if cplx else "f32"}[args.form],
+        "data": "synthetic",
+        "config": {
+            "workload": cfg.name,
+            "description": cfg.description,
+            "n": n, "nnz": A.nnz, "p": p, "degree": k, "damping": cfg.damping, "form": args.form,
+            "step": f"one solver iteration: filter ({k} products) + CholQR2 + Rayleigh-Ritz + residuals",
+        },
+        "pct_hbm_peak": round(100.0 * value / HBM_PEAK_GBS, 2),
+        "filter_only_gbs": round(filter_gbs, 1),
+        "filter_ms": round(filt_med, 3),
+        "roofline": {
+            "kernel": "clenshaw_step_kernel (steady state: gather src, read V in place, read X, write V)",
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "bytes_per_launch": steady_bytes,
+            "launch_us": round(steady_launch_ms * 1e3, 2),
+        },
+    }
+
+    if not args.no_solve:
+        out["solve"] = solve_rates(afsi, torch, dev)
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(A, p, k, lmin, lmax, a, b, cfg, sx, args.cpu_sample_steps)
+    M.close()
+    print(json.dumps(out), flush=True)
+
+
+def solve_rates(afsi, torch, dev):
+    """Eigenpairs/s of the full solver, FP64 vs mixed, on the converging 2D Laplacian workload."""
+    from workloads import build_config, start_block
+
+    A, (lmin, lmax), (a, b), cfg = build_config("lap2d_64")
+    # expected eigenvalues: the stored closed-form fixture of this window
+    fx = os.path.join(ROOT, "tests", "golden", "lap2d_64_window.txt")
+    exact = np.array([float(l.split()[1]) for l in open(fx) if not l.startswith("#")])
+    normA = max(abs(lmin), abs(lmax))
+    M = afsi.Matrix(A, device=0, bounds=(lmin, lmax))
+    X0 = start_block(A.n, cfg.p, seed=0)
+    out = {"workload": cfg.name, "n": A.n, "p": cfg.p, "degree": cfg.degree}
+    for form in ("fp64", "mixed"):
+        o = afsi.afsi_options_default(cfg.degree)
+        if form == "mixed":
+            o.filter_dtype = afsi.R32
+            o.tau_c = 1e-6
+        best = None
+        for rep in range(3):
+            X = torch.from_numpy(X0).to(dev)
+            E = torch.zeros((A.n, cfg.p), dtype=torch.float64, device=dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, lam, res, r = afsi.afsi_solve(M.handle, a, b, o, X, E, cfg.p)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            ok = st == 0 and lam.size == exact.size and np.max(np.abs(lam - exact)) <= 1e-5 * normA
+            good = int(lam.size) if ok else 0
+            rec = {"seconds": round(dt, 4), "eigenpairs": good, "iterations": r.iterations,
+                   "eigenpairs_per_s": round(good / dt, 2),
+                   "max_abs_eig_err": float(np.max(np.abs(lam - exact))) if lam.size == exact.size else None,
+                   "max_residual": float(np.max(res)) if res.size else None}
+            if best is None or rec["seconds"] < best["seconds"]:
+                best = rec
+        out[form] = best
+    M.close()
+    return out
+
+
+def cpu_baseline(A, p, k, lmin, lmax, a, b, cfg, sx, sample_steps):
+    """The oracle's Clenshaw filter on the same matrix, a few products, on the host cores."""
+    from oracle import coefficients as co
+    from oracle import native
+    from oracle.filter import clenshaw_steps
+    from workloads import start_block
+
+    native.build(force=False)
+    threads = native.num_threads()
+    X0 = start_block(A.n, p, seed=1)
+    c = co.filter_coefficients(lmin, lmax, a, b, k, cfg.damping)
+    l1, l2 = co.affine_map(lmin, lmax)
+    # size the sample to roughly 10-30 s of work: time one product first
+    gen = clenshaw_steps(A, X0, c, l1, l2)
+    t0 = time.perf_counter()
+    next(gen)
+    one = time.perf_counter() - t0
+    steps = sample_steps or max(2, min(k - 1, int(15.0 / max(one, 1e-3))))
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        next(gen)
+    dt = time.perf_counter() - t0
+    step_bytes = A.nnz * (8 + 4) + 4 * (A.n + 1) + 4 * A.n * p * 8
+    return {
+        "value": round(steps * step_bytes / dt / 1e9, 3),
+        "unit": "GB/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"{steps} Clenshaw products (of {k}) of the FP64 oracle on the full "
+                  f"{cfg.name} matrix, n={A.n}, p={p}; {dt:.1f} s",
+        "seconds_per_product": round(dt / steps, 4),
+    }
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,307 @@
+/*
+ * afsi.h -- C ABI of the MI355X (gfx950) library for adaptive Chebyshev-filtered
+ * subspace iteration on sparse Hermitian matrices.
+ *
+ * The method is the one of "Adaptive Polynomial Filtering for Hermitian Interior
+ * Eigenproblems: Convergence Analysis" (Xu, Ni, Li, Zhang): find every eigenpair
+ * (lambda, v) of a Hermitian A with lambda in [a, b] (Section 1, eq. (ori_problem))
+ * by subspace iteration on rho(A), where rho is a damped Chebyshev expansion of
+ * the interval's step function evaluated by Clenshaw's recurrence.
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ *  - Return value: AFSI_OK (0) or a negative afsi_status.  No C++ exception
+ *    crosses this boundary.  afsi_last_error() gives a message for the last
+ *    failure on the calling thread.
+ *  - Dense blocks (afsi_block) are caller-owned DEVICE memory, row-major: element
+ *    (i, j) is at ptr + i*ld + j (in elements, complex elements count once),
+ *    ld >= cols.  The library never frees or reallocates them.
+ *  - Matrices (afsi_matrix_t) are library-owned device copies made from host CSR.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Calls
+ *    that only produce device data are asynchronous on that stream.  Calls that
+ *    write host outputs synchronise that stream before returning.
+ *  - Host input arrays are read before the call returns; the caller keeps
+ *    ownership.
+ *  - Element types: real FP64 (R64), real FP32 (R32), complex FP64 (C128, pairs
+ *    of doubles re,im) and complex FP32 (C64, pairs of floats).  The filter runs
+ *    in the block's type; orthonormalisation, Rayleigh-Ritz and residuals are
+ *    FP64 (R64 or C128) only.
+ *  - Calls that overlap on one device must use different blocks; the library
+ *    keeps internal scratch per stream.
+ */
+#ifndef AFSI_H
+#define AFSI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    AFSI_OK = 0,
+    AFSI_E_INVALID = -1,   /* bad argument: shape, dtype, CSR structure, a >= b ... */
+    AFSI_E_NOMEM = -2,     /* device or host allocation failed */
+    AFSI_E_HIP = -3,       /* a HIP runtime call failed */
+    AFSI_E_NOT_HPD = -4,   /* Gram matrix not positive definite even after the shift */
+    AFSI_E_BOUNDS = -5,    /* filter output grew: spectral bounds do not enclose A */
+    AFSI_E_NOCONV = -6,    /* iteration limit reached; partial results returned */
+    AFSI_E_BUSY = -7,      /* serving: request does not fit the device budget now */
+    AFSI_E_NODEVICE = -8   /* no usable gfx950 device */
+} afsi_status;
+
+typedef enum { AFSI_R64 = 0, AFSI_R32 = 1, AFSI_C128 = 2, AFSI_C64 = 3 } afsi_dtype;
+
+typedef enum {
+    AFSI_DAMP_NONE = 0,     /* plain truncated Chebyshev series */
+    AFSI_DAMP_JACKSON = 1,  /* Jackson factors d^J_{j,k} (Section 2.2) */
+    AFSI_DAMP_LANCZOS = 2   /* exponent-m Lanczos factors, eq. (m_Lanczos_damping) */
+} afsi_damping;
+
+typedef struct afsi_matrix_s *afsi_matrix_t;
+
+/* A dense device block, row-major, `rows` x `cols` with row stride `ld` elements. */
+typedef struct {
+    void *ptr;
+    int64_t rows;
+    int64_t cols;
+    int64_t ld;
+    int32_t dtype; /* afsi_dtype */
+} afsi_block;
+
+/* ------------------------------------------------------------------ utilities */
+
+const char *afsi_last_error(void);   /* thread-local; never NULL */
+const char *afsi_version(void);
+/* Number of gfx950 devices visible, or a negative status. */
+int afsi_device_count(void);
+
+/* ------------------------------------------------------------------ matrices */
+
+/*
+ * Copy a square Hermitian CSR matrix from host memory to device `device`.
+ *   row_ptr[n+1] (int64, row_ptr[0] = 0, non-decreasing, row_ptr[n] = nnz),
+ *   col_idx[nnz] (int32, strictly increasing within each row, in [0, n)),
+ *   vals[nnz]    (val_dtype AFSI_R64: double; AFSI_C128: interleaved re,im doubles).
+ * The structure is validated (AFSI_E_INVALID on violation); Hermitian symmetry is
+ * the caller's promise and is not checked.  nnz must be below 2^31.
+ * An FP32 copy of the values is made on first use by an FP32 / C64 filter.
+ * Spectral bounds start unset (see afsi_set_spectral_bounds).
+ */
+int afsi_matrix_create_csr(int device, int64_t n, int64_t nnz, const int64_t *row_ptr,
+                           const int32_t *col_idx, const void *vals, int32_t val_dtype,
+                           afsi_matrix_t *out);
+int afsi_matrix_destroy(afsi_matrix_t A);
+/* n, nnz, value dtype (AFSI_R64 or AFSI_C128), device ordinal. Any output may be NULL. */
+int afsi_matrix_info(afsi_matrix_t A, int64_t *n, int64_t *nnz, int32_t *dtype, int32_t *device);
+
+/*
+ * Interval [lmin, lmax] enclosing the spectrum of A; defines the affine map
+ * l(x) = (2x - lmax - lmin) / (lmax - lmin) of Section 2.2.  Needs lmin < lmax.
+ */
+int afsi_set_spectral_bounds(afsi_matrix_t A, double lmin, double lmax);
+int afsi_get_spectral_bounds(afsi_matrix_t A, double *lmin, double *lmax);
+
+/*
+ * Estimate [lmin, lmax] by `steps` Lanczos steps with full reorthogonalisation
+ * from a start vector drawn from `seed` (Section 3.4 says "a few iterations").
+ * The extreme Ritz values are widened by their residual bound plus 1e-3 of the
+ * spread.  Stores the result in A (as afsi_set_spectral_bounds) and returns it.
+ */
+int afsi_estimate_spectral_bounds(afsi_matrix_t A, int steps, uint64_t seed, void *stream,
+                                  double *lmin, double *lmax);
+
+/* ------------------------------------------------------------------ filter */
+
+/*
+ * Filter coefficients a_j = c_j d_{j,kmax}, j = 0..kmax, written to coeffs[kmax+1]
+ * (host).  c_j from eq. (c_j) with alpha = arccos l(a), beta = arccos l(b), l(.)
+ * clipped into [-1, 1] (an interval reaching past the bounds is the extreme
+ * problem of Section 1); d_{j,kmax} Jackson, exponent-m Lanczos (m_exp >= 0) or
+ * none (Section 2.2).  A truncated filter of degree k^(i) <= kmax uses the first
+ * k^(i)+1 entries, as in eq. (AdaPolySI).  Pure host function.
+ */
+int afsi_filter_coefficients(double lmin, double lmax, double a, double b, int kmax,
+                             int32_t damping, double m_exp, double *coeffs);
+
+/*
+ * Y = sum_{j=0}^{degree} coeffs[j] T_j(l(A)) X  (Algorithm 2, Clenshaw's recurrence,
+ * in the division-free form b_{k+1} = b_{k+2} = 0, b_j = a_j X + 2 l(A) b_{j+1}
+ * - b_{j+2}, Y = a_0 X + l(A) b_1 - b_2), using exactly `degree` products with A.
+ *   coeffs : host, degree+1 doubles (cast to FP32 for R32 / C64 blocks).
+ *   X, Y, work : n x p blocks of one dtype; R64/R32 for a real A, C128/C64 for a
+ *   complex A.  Y and work are overwritten; none of X, Y, work may overlap.
+ * Needs spectral bounds on A and degree >= 1.  Asynchronous on `stream`.
+ */
+int afsi_filter_block(afsi_matrix_t A, const double *coeffs, int degree, const afsi_block *X,
+                      afsi_block *Y, afsi_block *work, void *stream);
+
+/* Y = A X (one sparse x dense-block product). X and Y as for afsi_filter_block. */
+int afsi_spmm(afsi_matrix_t A, const afsi_block *X, afsi_block *Y, void *stream);
+
+/*
+ * One Clenshaw product for a column group of concatenated blocks:
+ *   dst = sigma * A * src + tau * src - (has_v ? dst : 0) + alpha * X
+ * on columns [col0, col0 + ncols) of the buffers, with src selected from
+ * {X, P0, P1} and dst from {P0, P1}.  afsi_clenshaw_step_params fills
+ * (src, dst, has_v, sigma, tau, alpha) for product number `step` (0..degree-1)
+ * of a degree-`degree` filter so that the last product writes Y to
+ * P[(degree-1) % 2].
+ */
+typedef struct {
+    int64_t col0, ncols;
+    int32_t src;    /* 0 = X, 1 = P0, 2 = P1 */
+    int32_t dst;    /* 1 = P0, 2 = P1 (never equal to src) */
+    int32_t has_v;  /* subtract the previous contents of dst (b_{j+2}) */
+    int32_t active; /* 0: leave these columns untouched */
+    double sigma, tau, alpha;
+} afsi_step_group;
+
+int afsi_clenshaw_step_params(const double *coeffs, int degree, int step, double l1, double l2,
+                              afsi_step_group *g);
+
+/*
+ * Batched step for spectrum slices of one matrix (several filters advanced
+ * together, A read once).  X, P0, P1: n x ptot blocks of one dtype.  Groups must
+ * not overlap; at most 64.  Columns outside every active group are untouched.
+ * Per column the arithmetic is identical to afsi_filter_block's, so a slice gives
+ * bit-identical results alone or batched.
+ */
+int afsi_clenshaw_step_batched(afsi_matrix_t A, int ngroups, const afsi_step_group *groups,
+                               const afsi_block *X, afsi_block *P0, afsi_block *P1, void *stream);
+
+/* ------------------------------------------------------------------ dense steps (FP64) */
+
+/*
+ * G = X^H Y (p x q) for n x p X and n x q Y (R64 or C128, same dtype), into the
+ * device block G (p x q, same dtype).  Fixed-order reduction: deterministic.
+ */
+int afsi_block_inner(const afsi_block *X, const afsi_block *Y, afsi_block *G, void *stream);
+
+/*
+ * Y = X M + beta Y for n x p X, p x q M (device), n x q Y; R64 or C128; beta real.
+ * Y must not overlap X or M.
+ */
+int afsi_block_gemm(const afsi_block *X, const afsi_block *M, double beta, afsi_block *Y,
+                    void *stream);
+
+/*
+ * Orthonormalise X in place (Algorithm 4, orthogonalisation step, by Cholesky QR):
+ * first X <- X - L (L^H X) twice when `locked` has columns (L orthonormal), then
+ * CholQR2 (G = X^H X, R^H R = G, X <- X R^-1, repeated once).  If a Cholesky
+ * factor breaks down, shifted CholQR3 is used (shift 11 (n p + p (p+1)) u ||X||_F^2).
+ * `work` is an n x p scratch block of X's dtype.  R64 or C128.
+ * Synchronises `stream` (the small Gram factorisations run on the host).
+ */
+int afsi_orthonormalize(const afsi_block *locked, afsi_block *X, afsi_block *work, void *stream);
+
+/*
+ * Rayleigh-Ritz (Algorithm 1): B = Q^H A Q, B = U diag(ritz) U^H (host, FP64),
+ * V = Q U and AV = (A Q) U.  Q is n x p orthonormal and left unchanged; V and AV
+ * are n x p; ritz_out[p] (host) ascending.  R64 or C128.  Synchronises `stream`.
+ */
+int afsi_rayleigh_ritz(afsi_matrix_t A, const afsi_block *Q, afsi_block *V, afsi_block *AV,
+                       double *ritz_out, void *stream);
+
+/*
+ * norms_out[j] = || AV[:, j] - lambda[j] V[:, j] ||_2 for j < V.cols (host output,
+ * Algorithm 4 residual step).  R64 or C128.  Synchronises `stream`.
+ */
+int afsi_residual_norms(const afsi_block *V, const afsi_block *AV, const double *lambda,
+                        double *norms_out, void *stream);
+
+/* dst = src converted (R64 <-> R32, C128 <-> C64, or same type copy); same shape. */
+int afsi_convert_block(const afsi_block *src, afsi_block *dst, void *stream);
+
+/* dst[:, t] = src[:, cols[t]] for t < count (host index list); dst has count columns. */
+int afsi_gather_columns(const afsi_block *src, const int32_t *cols, int64_t count,
+                        afsi_block *dst, void *stream);
+
+/* ------------------------------------------------------------------ host control */
+
+/*
+ * Algorithm 3: the first j in 1..kmax for which the truncated series
+ * gamma = sum_{i<=j} coeffs[i] T_i(l(ritz)) satisfies |gamma|_(p) / |gamma|_(e) < tau_a
+ * (p-th and e-th largest magnitudes over the p Ritz values); kmax if none.
+ * Needs 1 <= e <= p.  Pure host function.
+ */
+int afsi_select_degree(const double *ritz, int64_t p, int64_t e, const double *coeffs, int kmax,
+                       double l1, double l2, double tau_a, int *degree_out);
+
+/*
+ * Spurious-value test and locking of one iteration (Algorithm 4 with eq. (tau_s)):
+ *   in_interval[j] (in, length p): 1 if ritz[j] in [a, b];
+ *   res[j]: residual norms (read where in_interval[j]);
+ *   tau_s = min over the interval's Ritz values of the distance to {a, b};
+ *   C = {j in I : res[j] < tau_s}; n_check = |C| + n_lock; if n_check > 0 and it
+ *   equals *n_check_prev, I = C; *n_check_prev = n_check;
+ *   lock[j] = (j in I and res[j] < tau_abs); in_interval is overwritten with I;
+ *   *done = (I minus the locked set is empty).
+ * Pure host function; requires at least one in_interval entry.
+ */
+int afsi_lock_select(const double *ritz, int64_t p, const double *res, uint8_t *in_interval,
+                     double a, double b, double tau_abs, int64_t n_lock, int64_t *n_check_prev,
+                     uint8_t *lock, int *done);
+
+/*
+ * Host Hermitian eigensolver used by Rayleigh-Ritz (Algorithm 1): B (p x p,
+ * row-major, ldb; R64 or C128, only its Hermitian part is used) = U diag(w) U^H,
+ * w[p] ascending, U (p x p, ldu, same dtype) unitary.  Householder tridiagonal
+ * reduction + implicit-shift symmetric QR.  Pure host function.
+ */
+int afsi_host_eigh(int64_t p, int32_t dtype, const double *B, int64_t ldb, double *w, double *U,
+                   int64_t ldu);
+
+/*
+ * Host factor used by Cholesky QR: overwrite G (p x p Hermitian positive definite,
+ * row-major, R64 or C128) with R^{-1}, where R^H R = G + shift I and R is upper
+ * triangular (the strictly lower part is set to zero).  AFSI_E_NOT_HPD (and G
+ * unchanged) on a non-positive pivot.  Pure host function.
+ */
+int afsi_host_cholesky_inverse(int64_t p, int32_t dtype, double *G, int64_t ldg, double shift);
+
+/* ------------------------------------------------------------------ full solver */
+
+typedef struct {
+    int32_t kmax;          /* maximum degree k (coefficients and damping use it) */
+    int32_t k_init;        /* first degree; <= 0: kmax (fixed) or eq. (compute_k_1) (adaptive) */
+    int32_t adaptive;      /* 1: Algorithm 3 after each iteration; 0: fixed degree */
+    int32_t damping;       /* afsi_damping */
+    double m_exp;          /* exponent m for AFSI_DAMP_LANCZOS (paper: 0.5) */
+    double tau_a;          /* Algorithm 3 threshold (paper: 1e-3) */
+    double tau_c;          /* lock when ||r|| < tau_c * ||A||, ||A|| = max(|lmin|,|lmax|) */
+    double C;              /* eq. (compute_k_1) constant (paper: 1.4) */
+    int32_t max_iter;      /* iteration limit */
+    int32_t filter_dtype;  /* AFSI_R64/AFSI_C128 (plain) or AFSI_R32/AFSI_C64 (mixed form) */
+} afsi_options;
+
+/* Fill `o` with the paper's parameters (Section 4) and a fixed Jackson degree kmax. */
+void afsi_options_default(afsi_options *o, int kmax);
+
+typedef struct {
+    int64_t count;         /* eigenpairs found in [a, b] */
+    int32_t iterations;
+    int32_t converged;     /* 1 if every Ritz pair in [a, b] was locked */
+    int64_t spmv;          /* products with A times block columns (filter + Rayleigh-Ritz) */
+    double avg_degree;
+    double time_filter_ms, time_orth_ms, time_rr_ms, time_resid_ms, time_host_ms;
+} afsi_result;
+
+/*
+ * Algorithm 4 on A with bounds already set.  X0: n x p start block (FP64 dtype of
+ * A's domain, device); it is orthonormalised and then consumed (overwritten).
+ * On return: eigenvalues[count] (host, ascending, capacity `capacity`),
+ * residuals[count] (host), and the eigenvectors in columns 0..count-1 of
+ * `evecs` (device, n x capacity, FP64 dtype).  Returns AFSI_E_NOCONV with the
+ * pairs locked so far if max_iter is reached, AFSI_E_INVALID if more than
+ * `capacity` pairs lock.
+ */
+int afsi_solve(afsi_matrix_t A, double a, double b, const afsi_options *opts, afsi_block *X0,
+               afsi_block *evecs, int64_t capacity, double *eigenvalues, double *residuals,
+               afsi_result *result, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AFSI_H */

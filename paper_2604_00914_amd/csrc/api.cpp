@@ -1,0 +1,746 @@
+// C ABI of the library: argument checking, resource management and the host side
+// of each call.  The arithmetic of the hot path runs in the HIP kernels
+// (clenshaw_*.hip, dense.hip, util.hip); small p x p factorisations run on the host
+// (host_linalg.cpp).
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <limits>
+#include <map>
+#include <memory>
+#include <utility>
+#include <vector>
+
+#include "clenshaw_kernels.h"
+#include "internal.h"
+
+namespace afsi {
+
+// ---------------------------------------------------------------- errors
+
+static thread_local std::string g_error = "no error";
+
+void set_error(const char *fmt, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_error = buf;
+}
+
+// ---------------------------------------------------------------- device / scratch
+
+DeviceGuard::DeviceGuard(int dev) {
+    AFSI_HIP(hipGetDevice(&prev));
+    if (prev != dev) AFSI_HIP(hipSetDevice(dev));
+    else prev = -1;
+}
+DeviceGuard::~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+}
+
+void *Workspace::dev_reserve(int slot, size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    if (bytes > dev_bytes[slot]) {
+        if (dev[slot]) {
+            AFSI_HIP(hipStreamSynchronize(stream));
+            AFSI_HIP(hipFree(dev[slot]));
+            dev[slot] = nullptr;
+            dev_bytes[slot] = 0;
+        }
+        const size_t want = std::max(bytes, dev_bytes[slot] + dev_bytes[slot] / 2);
+        AFSI_HIP(hipMalloc(&dev[slot], want));
+        dev_bytes[slot] = want;
+    }
+    return dev[slot];
+}
+
+void *Workspace::host_reserve(int slot, size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    if (bytes > host_bytes[slot]) {
+        if (host[slot]) {
+            AFSI_HIP(hipStreamSynchronize(stream));
+            AFSI_HIP(hipHostFree(host[slot]));
+            host[slot] = nullptr;
+            host_bytes[slot] = 0;
+        }
+        AFSI_HIP(hipHostMalloc(&host[slot], bytes, hipHostMallocDefault));
+        host_bytes[slot] = bytes;
+    }
+    return host[slot];
+}
+
+static std::mutex g_ws_mu;
+static std::map<std::pair<int, hipStream_t>, std::unique_ptr<Workspace>> g_ws;
+
+Workspace &workspace(hipStream_t stream) {
+    int dev = 0;
+    AFSI_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    auto &slot = g_ws[{dev, stream}];
+    if (!slot) {
+        slot.reset(new Workspace());
+        slot->stream = stream;
+    }
+    return *slot;
+}
+
+// ---------------------------------------------------------------- matrix access
+
+MatView matrix_view(afsi_matrix_t A, int block_dtype, hipStream_t stream) {
+    const bool want_complex = is_complex(block_dtype);
+    AFSI_REQUIRE(want_complex == (A->dtype == AFSI_C128),
+                 "block dtype %d does not match the matrix (%s)", block_dtype,
+                 A->dtype == AFSI_C128 ? "complex" : "real");
+    MatView v{A->n, A->d_rp, A->d_ci, A->d_val64};
+    if (!is_fp64(block_dtype)) {
+        std::lock_guard<std::mutex> lk(A->mu);
+        if (!A->d_val32) {
+            const int64_t count = A->nnz * (want_complex ? 2 : 1);
+            AFSI_HIP(hipMalloc(&A->d_val32, std::max<int64_t>(count, 1) * sizeof(float)));
+            launch_to_f32((const double *)A->d_val64, (float *)A->d_val32, count, stream);
+            AFSI_HIP(hipStreamSynchronize(stream));
+        }
+        v.val = A->d_val32;
+    }
+    return v;
+}
+
+// ---------------------------------------------------------------- block checks
+
+static hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+static void check_block(const afsi_block *b, const char *name) {
+    AFSI_REQUIRE(b != nullptr, "%s is NULL", name);
+    AFSI_REQUIRE(b->dtype >= AFSI_R64 && b->dtype <= AFSI_C64, "%s has unknown dtype %d", name,
+                 b->dtype);
+    AFSI_REQUIRE(b->rows >= 0 && b->cols >= 0, "%s has negative shape", name);
+    AFSI_REQUIRE(b->ld >= b->cols && b->ld >= 1, "%s: ld (%lld) < cols (%lld)", name,
+                 (long long)b->ld, (long long)b->cols);
+    AFSI_REQUIRE(b->ptr != nullptr || b->rows * b->cols == 0, "%s has a NULL pointer", name);
+}
+
+static void check_fp64(const afsi_block *b, const char *name) {
+    AFSI_REQUIRE(is_fp64(b->dtype), "%s must be R64 or C128 (got dtype %d)", name, b->dtype);
+}
+
+static std::pair<uintptr_t, uintptr_t> span(const afsi_block *b) {
+    const uintptr_t p = (uintptr_t)b->ptr;
+    if (b->rows * b->cols == 0) return {p, p};
+    return {p, p + (uintptr_t)(((b->rows - 1) * b->ld + b->cols) * elem_bytes(b->dtype))};
+}
+
+static bool overlap(const afsi_block *a, const afsi_block *b) {
+    auto x = span(a), y = span(b);
+    return x.first < y.second && y.first < x.second;
+}
+
+static void check_same_shape(const afsi_block *a, const afsi_block *b, const char *na,
+                             const char *nb) {
+    AFSI_REQUIRE(a->rows == b->rows && a->cols == b->cols && a->ld == b->ld && a->dtype == b->dtype,
+                 "%s and %s must have the same shape, leading dimension and dtype", na, nb);
+}
+
+// ---------------------------------------------------------------- Clenshaw step launch
+
+static bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
+
+static void run_step(const MatView &mv, int dtype, const void *src, const void *X, void *dst,
+                     int64_t p, int64_t ld, bool hv, bool hx, double sg, double ta, double al,
+                     hipStream_t s) {
+    if (mv.n == 0 || p == 0) return;
+    AFSI_REQUIRE(p < (1LL << 31) && ld < (1LL << 40), "block too wide");
+    const int eb = elem_bytes(dtype);
+    const bool vec = (p * eb) % 16 == 0 && (ld * eb) % 16 == 0 && aligned16(src) &&
+                     aligned16(dst) && (!hx || aligned16(X));
+    if (vec) {
+        const int p16 = (int)(p * eb / 16);
+        const int64_t ldv = ld * eb / 16;
+        switch (dtype) {
+        case AFSI_R64: clenshaw_r64_step(mv, src, X, dst, p16, ldv, hv, hx, sg, ta, al, s); break;
+        case AFSI_R32: clenshaw_r32_step(mv, src, X, dst, p16, ldv, hv, hx, sg, ta, al, s); break;
+        case AFSI_C128: clenshaw_c128_step(mv, src, X, dst, p16, ldv, hv, hx, sg, ta, al, s); break;
+        case AFSI_C64: clenshaw_c64_step(mv, src, X, dst, p16, ldv, hv, hx, sg, ta, al, s); break;
+        }
+    } else {
+        const int pi = (int)p;
+        switch (dtype) {
+        case AFSI_R64: clenshaw_r64_scalar(mv, src, X, dst, pi, ld, hv, hx, sg, ta, al, s); break;
+        case AFSI_R32: clenshaw_r32_scalar(mv, src, X, dst, pi, ld, hv, hx, sg, ta, al, s); break;
+        case AFSI_C128: clenshaw_c128_scalar(mv, src, X, dst, pi, ld, hv, hx, sg, ta, al, s); break;
+        case AFSI_C64: clenshaw_c64_scalar(mv, src, X, dst, pi, ld, hv, hx, sg, ta, al, s); break;
+        }
+    }
+    AFSI_HIP(hipGetLastError());
+}
+
+static void map_coeffs(const afsi_matrix_s *A, double &l1, double &l2) {
+    AFSI_REQUIRE(A->has_bounds, "spectral bounds are not set on this matrix");
+    const double w = A->lmax - A->lmin;
+    l1 = 2.0 / w;
+    l2 = -(A->lmax + A->lmin) / w;
+}
+
+static void check_matrix(afsi_matrix_t A) { AFSI_REQUIRE(A != nullptr, "matrix handle is NULL"); }
+
+// Filter on raw pointers (shared by afsi_filter_block and the solver).
+void filter_apply(afsi_matrix_t A, const double *coeffs, int degree, int dtype, const void *X,
+                  void *Y, void *work, int64_t p, int64_t ld, hipStream_t s) {
+    double l1, l2;
+    map_coeffs(A, l1, l2);
+    AFSI_REQUIRE(degree >= 1, "degree must be >= 1 (got %d)", degree);
+    const MatView mv = matrix_view(A, dtype, s);
+    void *P[3] = {const_cast<void *>(X), nullptr, nullptr};
+    P[1 + (degree - 1) % 2] = Y;
+    P[1 + degree % 2] = work;
+    for (int st = 0; st < degree; ++st) {
+        afsi_step_group g;
+        step_params(coeffs, degree, st, l1, l2, &g);
+        run_step(mv, dtype, P[g.src], X, P[g.dst], p, ld, g.has_v != 0, g.alpha != 0.0, g.sigma,
+                 g.tau, g.alpha, s);
+    }
+}
+
+void spmm_apply(afsi_matrix_t A, int dtype, const void *X, void *Y, int64_t p, int64_t ld,
+                hipStream_t s) {
+    const MatView mv = matrix_view(A, dtype, s);
+    run_step(mv, dtype, X, nullptr, Y, p, ld, false, false, 1.0, 0.0, 0.0, s);
+}
+
+// ---------------------------------------------------------------- dense helpers
+
+void inner_dev(int dtype, const void *X, int64_t ldx, const void *Y, int64_t ldy, int64_t n,
+               int64_t p, int64_t q, double *G, int64_t ldg, hipStream_t s) {
+    if (dtype == AFSI_C128)
+        gram_c128((const double *)X, ldx, (const double *)Y, ldy, n, p, q, G, ldg, s);
+    else
+        gram_f64((const double *)X, ldx, (const double *)Y, ldy, n, p, q, G, ldg, s);
+}
+
+void gemm_dev(int dtype, const void *X, int64_t ldx, const double *M, int64_t ldm, int64_t n,
+              int64_t p, int64_t q, double alpha, double beta, void *Y, int64_t ldy,
+              hipStream_t s) {
+    if (dtype == AFSI_C128)
+        gemm_c128((const double *)X, ldx, M, ldm, n, p, q, alpha, beta, (double *)Y, ldy, s);
+    else
+        gemm_f64((const double *)X, ldx, M, ldm, n, p, q, alpha, beta, (double *)Y, ldy, s);
+}
+
+// X <- X - L (L^H X), twice.  L: n x k (ld ldl), X: n x p (ld ldx).
+void project_out_dev(int dtype, const void *L, int64_t ldl, int64_t k, void *X, int64_t ldx,
+                     int64_t n, int64_t p, hipStream_t s) {
+    if (k == 0 || p == 0) return;
+    const int comp = dtype == AFSI_C128 ? 2 : 1;
+    double *C = (double *)workspace(s).dev_reserve(SLOT_SMALL, sizeof(double) * comp * k * p);
+    for (int pass = 0; pass < 2; ++pass) {
+        inner_dev(dtype, L, ldl, X, ldx, n, k, p, C, p, s);
+        gemm_dev(dtype, L, ldl, C, p, n, k, p, -1.0, 1.0, X, ldx, s);
+    }
+}
+
+// CholQR2 with shifted CholQR3 fallback.  X and W: n x p, same ld.  Result in X.
+// max_col_norm2 (optional): largest squared column norm of X on entry.
+void orthonormalize_dev(int dtype, void *X, void *W, int64_t n, int64_t p, int64_t ld,
+                        hipStream_t s, double *max_col_norm2) {
+    if (p == 0) return;
+    const bool cplx = dtype == AFSI_C128;
+    const int comp = cplx ? 2 : 1;
+    const size_t gbytes = sizeof(double) * comp * p * p;
+    Workspace &ws = workspace(s);
+    double *G = (double *)ws.dev_reserve(SLOT_SMALL, gbytes);
+    double *Gh = (double *)ws.host_reserve(0, gbytes);
+    void *cur = X, *oth = W;
+    const double u = std::numeric_limits<double>::epsilon() / 2;
+    int plain_passes = 0, shifted = 0;
+    while (plain_passes < 2) {
+        inner_dev(dtype, cur, ld, cur, ld, n, p, p, G, p, s);
+        AFSI_HIP(hipMemcpyAsync(Gh, G, gbytes, hipMemcpyDeviceToHost, s));
+        AFSI_HIP(hipStreamSynchronize(s));
+        if (max_col_norm2 && cur == X && plain_passes == 0 && shifted == 0) {
+            double mx = 0.0;
+            for (int64_t i = 0; i < p; ++i) mx = std::max(mx, Gh[comp * (i * p + i)]);
+            *max_col_norm2 = mx;
+        }
+        // host_cholesky_inverse leaves Gh untouched when it reports a breakdown
+        if (host_cholesky_inverse(p, cplx, Gh, p, 0.0)) {
+            ++plain_passes;
+        } else {
+            // shifted Cholesky QR (Fukaya et al. 2020): s = 11 (n p + p (p+1)) u ||X||_F^2,
+            // followed by two plain passes
+            if (shifted >= 2) AFSI_FAIL(AFSI_E_NOT_HPD, "Cholesky QR broke down even with a shift");
+            double fro2 = 0.0;
+            for (int64_t i = 0; i < p; ++i) fro2 += Gh[comp * (i * p + i)];
+            const double shift = 11.0 * ((double)n * p + (double)p * (p + 1)) * u * fro2;
+            if (!host_cholesky_inverse(p, cplx, Gh, p, shift))
+                AFSI_FAIL(AFSI_E_NOT_HPD, "Cholesky QR broke down even with a shift");
+            ++shifted;
+            plain_passes = 0;
+        }
+        AFSI_HIP(hipMemcpyAsync(G, Gh, gbytes, hipMemcpyHostToDevice, s));
+        gemm_dev(dtype, cur, ld, G, p, n, p, p, 1.0, 0.0, oth, ld, s);
+        std::swap(cur, oth);
+    }
+    if (cur != X) {
+        const int eb = elem_bytes(dtype);
+        AFSI_HIP(hipMemcpy2DAsync(X, ld * eb, cur, ld * eb, p * eb, n, hipMemcpyDeviceToDevice, s));
+    }
+    AFSI_HIP(hipStreamSynchronize(s));
+}
+
+// Rayleigh-Ritz on raw pointers.  Q, V, AV: n x p with leading dimension ld.
+void rayleigh_ritz_dev(afsi_matrix_t A, int dtype, const void *Q, void *V, void *AV, int64_t n,
+                       int64_t p, int64_t ld, double *ritz, hipStream_t s) {
+    if (p == 0) return;
+    const bool cplx = dtype == AFSI_C128;
+    const int comp = cplx ? 2 : 1;
+    const size_t mbytes = sizeof(double) * comp * p * p;
+    Workspace &ws = workspace(s);
+    double *B = (double *)ws.dev_reserve(SLOT_SMALL, mbytes);
+    double *Bh = (double *)ws.host_reserve(0, 2 * mbytes);
+    double *Uh = Bh + comp * p * p;
+    spmm_apply(A, dtype, Q, V, p, ld, s);                  // V <- A Q
+    inner_dev(dtype, Q, ld, V, ld, n, p, p, B, p, s);      // B <- Q^H A Q
+    AFSI_HIP(hipMemcpyAsync(Bh, B, mbytes, hipMemcpyDeviceToHost, s));
+    AFSI_HIP(hipStreamSynchronize(s));
+    host_eigh(p, cplx, Bh, p, ritz, Uh, p);
+    AFSI_HIP(hipMemcpyAsync(B, Uh, mbytes, hipMemcpyHostToDevice, s));
+    gemm_dev(dtype, V, ld, B, p, n, p, p, 1.0, 0.0, AV, ld, s);  // AV <- (A Q) U
+    gemm_dev(dtype, Q, ld, B, p, n, p, p, 1.0, 0.0, V, ld, s);   // V  <- Q U
+    AFSI_HIP(hipStreamSynchronize(s));
+}
+
+void residual_norms_host(int dtype, const void *V, int64_t ldv, const void *AV, int64_t ldav,
+                         const double *lambda, int64_t n, int64_t q, double *out, hipStream_t s) {
+    if (q == 0) return;
+    Workspace &ws = workspace(s);
+    double *d = (double *)ws.dev_reserve(SLOT_VEC, sizeof(double) * 2 * q);
+    double *h = (double *)ws.host_reserve(1, sizeof(double) * q);
+    std::memcpy(h, lambda, sizeof(double) * q);
+    AFSI_HIP(hipMemcpyAsync(d, h, sizeof(double) * q, hipMemcpyHostToDevice, s));
+    residual_norms_dev(dtype, V, ldv, AV, ldav, d, n, q, d + q, s);
+    AFSI_HIP(hipMemcpyAsync(h, d + q, sizeof(double) * q, hipMemcpyDeviceToHost, s));
+    AFSI_HIP(hipStreamSynchronize(s));
+    std::memcpy(out, h, sizeof(double) * q);
+}
+
+// Spurious-value and locking test (shared by afsi_lock_select and the solver).
+void lock_select(const double *ritz, int64_t p, const double *res, uint8_t *I, double a, double b,
+                 double tau_abs, int64_t n_lock, int64_t *n_check_prev, uint8_t *lock, int *done) {
+    double tau_s = INFINITY;
+    int64_t e = 0;
+    for (int64_t j = 0; j < p; ++j)
+        if (I[j]) {
+            tau_s = std::min(tau_s, std::min(std::fabs(ritz[j] - a), std::fabs(ritz[j] - b)));
+            ++e;
+        }
+    AFSI_REQUIRE(e > 0, "no Ritz value inside the interval");
+    int64_t nc = 0;
+    for (int64_t j = 0; j < p; ++j)
+        if (I[j] && res[j] < tau_s) ++nc;
+    const int64_t n_check = nc + n_lock;
+    if (n_check > 0 && n_check == *n_check_prev)
+        for (int64_t j = 0; j < p; ++j) I[j] = (I[j] && res[j] < tau_s) ? 1 : 0;
+    *n_check_prev = n_check;
+    int left = 0;
+    for (int64_t j = 0; j < p; ++j) {
+        lock[j] = (I[j] && res[j] < tau_abs) ? 1 : 0;
+        if (I[j] && !lock[j]) left = 1;
+    }
+    *done = left ? 0 : 1;
+}
+
+}  // namespace afsi
+
+using namespace afsi;
+
+// ====================================================================== C ABI
+
+extern "C" {
+
+const char *afsi_last_error(void) { return g_error.c_str(); }
+
+const char *afsi_version(void) { return "afsi 0.1 (gfx950)"; }
+
+int afsi_device_count(void) {
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess) {
+        set_error("hipGetDeviceCount failed");
+        return AFSI_E_NODEVICE;
+    }
+    int count = 0;
+    for (int d = 0; d < n; ++d) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, d) == hipSuccess &&
+            std::strncmp(prop.gcnArchName, "gfx950", 6) == 0)
+            ++count;
+    }
+    return count;
+}
+
+int afsi_matrix_create_csr(int device, int64_t n, int64_t nnz, const int64_t *row_ptr,
+                           const int32_t *col_idx, const void *vals, int32_t val_dtype,
+                           afsi_matrix_t *out) {
+    return guarded([&] {
+        AFSI_REQUIRE(out != nullptr, "out is NULL");
+        *out = nullptr;
+        AFSI_REQUIRE(n >= 0 && nnz >= 0, "negative size");
+        AFSI_REQUIRE(n < (1LL << 31) && nnz < (1LL << 31), "n and nnz must be below 2^31");
+        AFSI_REQUIRE(val_dtype == AFSI_R64 || val_dtype == AFSI_C128,
+                     "values must be R64 or C128 (got %d)", val_dtype);
+        AFSI_REQUIRE(row_ptr != nullptr, "row_ptr is NULL");
+        AFSI_REQUIRE(nnz == 0 || (col_idx && vals), "col_idx / vals are NULL");
+        AFSI_REQUIRE(row_ptr[0] == 0 && row_ptr[n] == nnz, "row_ptr must start at 0 and end at nnz");
+        std::vector<int> rp32(n + 1);
+        for (int64_t i = 0; i < n; ++i) {
+            AFSI_REQUIRE(row_ptr[i + 1] >= row_ptr[i], "row_ptr decreases at row %lld", (long long)i);
+            for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+                AFSI_REQUIRE(col_idx[e] >= 0 && col_idx[e] < n, "column %d out of range in row %lld",
+                             col_idx[e], (long long)i);
+                AFSI_REQUIRE(e == row_ptr[i] || col_idx[e] > col_idx[e - 1],
+                             "columns not strictly increasing in row %lld", (long long)i);
+            }
+            rp32[i] = (int)row_ptr[i];
+        }
+        rp32[n] = (int)nnz;
+        DeviceGuard dg(device);
+        std::unique_ptr<afsi_matrix_s> A(new afsi_matrix_s());
+        A->device = device;
+        A->n = n;
+        A->nnz = nnz;
+        A->dtype = val_dtype;
+        const size_t vbytes = (size_t)nnz * elem_bytes(val_dtype);
+        try {
+            AFSI_HIP(hipMalloc(&A->d_rp, sizeof(int) * (n + 1)));
+            AFSI_HIP(hipMalloc(&A->d_ci, sizeof(int) * std::max<int64_t>(nnz, 1)));
+            AFSI_HIP(hipMalloc(&A->d_val64, std::max<size_t>(vbytes, 16)));
+            AFSI_HIP(hipMemcpy(A->d_rp, rp32.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice));
+            if (nnz) {
+                AFSI_HIP(hipMemcpy(A->d_ci, col_idx, sizeof(int) * nnz, hipMemcpyHostToDevice));
+                AFSI_HIP(hipMemcpy(A->d_val64, vals, vbytes, hipMemcpyHostToDevice));
+            }
+        } catch (...) {
+            (void)hipFree(A->d_rp);
+            (void)hipFree(A->d_ci);
+            (void)hipFree(A->d_val64);
+            throw;
+        }
+        *out = A.release();
+    });
+}
+
+int afsi_matrix_destroy(afsi_matrix_t A) {
+    return guarded([&] {
+        if (!A) return;
+        DeviceGuard dg(A->device);
+        AFSI_HIP(hipDeviceSynchronize());
+        (void)hipFree(A->d_rp);
+        (void)hipFree(A->d_ci);
+        (void)hipFree(A->d_val64);
+        if (A->d_val32) (void)hipFree(A->d_val32);
+        delete A;
+    });
+}
+
+int afsi_matrix_info(afsi_matrix_t A, int64_t *n, int64_t *nnz, int32_t *dtype, int32_t *device) {
+    return guarded([&] {
+        check_matrix(A);
+        if (n) *n = A->n;
+        if (nnz) *nnz = A->nnz;
+        if (dtype) *dtype = A->dtype;
+        if (device) *device = A->device;
+    });
+}
+
+int afsi_set_spectral_bounds(afsi_matrix_t A, double lmin, double lmax) {
+    return guarded([&] {
+        check_matrix(A);
+        AFSI_REQUIRE(std::isfinite(lmin) && std::isfinite(lmax) && lmin < lmax,
+                     "bounds need finite lmin < lmax (got %g, %g)", lmin, lmax);
+        A->lmin = lmin;
+        A->lmax = lmax;
+        A->has_bounds = true;
+    });
+}
+
+int afsi_get_spectral_bounds(afsi_matrix_t A, double *lmin, double *lmax) {
+    return guarded([&] {
+        check_matrix(A);
+        AFSI_REQUIRE(A->has_bounds, "spectral bounds are not set");
+        if (lmin) *lmin = A->lmin;
+        if (lmax) *lmax = A->lmax;
+    });
+}
+
+int afsi_filter_coefficients(double lmin, double lmax, double a, double b, int kmax,
+                             int32_t damping, double m_exp, double *coeffs) {
+    return guarded([&] {
+        AFSI_REQUIRE(coeffs != nullptr, "coeffs is NULL");
+        filter_coefficients(lmin, lmax, a, b, kmax, damping, m_exp, coeffs);
+    });
+}
+
+int afsi_filter_block(afsi_matrix_t A, const double *coeffs, int degree, const afsi_block *X,
+                      afsi_block *Y, afsi_block *work, void *stream) {
+    return guarded([&] {
+        check_matrix(A);
+        AFSI_REQUIRE(coeffs != nullptr, "coeffs is NULL");
+        check_block(X, "X");
+        check_block(Y, "Y");
+        check_block(work, "work");
+        check_same_shape(X, Y, "X", "Y");
+        check_same_shape(X, work, "X", "work");
+        AFSI_REQUIRE(X->rows == A->n, "X has %lld rows, A has %lld", (long long)X->rows,
+                     (long long)A->n);
+        AFSI_REQUIRE(!overlap(X, Y) && !overlap(X, work) && !overlap(Y, work),
+                     "X, Y and work must not overlap");
+        DeviceGuard dg(A->device);
+        filter_apply(A, coeffs, degree, X->dtype, X->ptr, Y->ptr, work->ptr, X->cols, X->ld,
+                     as_stream(stream));
+    });
+}
+
+int afsi_spmm(afsi_matrix_t A, const afsi_block *X, afsi_block *Y, void *stream) {
+    return guarded([&] {
+        check_matrix(A);
+        check_block(X, "X");
+        check_block(Y, "Y");
+        check_same_shape(X, Y, "X", "Y");
+        AFSI_REQUIRE(X->rows == A->n, "X rows != n");
+        AFSI_REQUIRE(!overlap(X, Y), "X and Y must not overlap");
+        DeviceGuard dg(A->device);
+        spmm_apply(A, X->dtype, X->ptr, Y->ptr, X->cols, X->ld, as_stream(stream));
+    });
+}
+
+int afsi_clenshaw_step_params(const double *coeffs, int degree, int step, double l1, double l2,
+                              afsi_step_group *g) {
+    return guarded([&] {
+        AFSI_REQUIRE(coeffs && g, "NULL argument");
+        const int64_t c0 = g->col0, nc = g->ncols;
+        step_params(coeffs, degree, step, l1, l2, g);
+        g->col0 = c0;
+        g->ncols = nc;
+    });
+}
+
+int afsi_clenshaw_step_batched(afsi_matrix_t A, int ngroups, const afsi_step_group *groups,
+                               const afsi_block *X, afsi_block *P0, afsi_block *P1, void *stream) {
+    return guarded([&] {
+        check_matrix(A);
+        check_block(X, "X");
+        check_block(P0, "P0");
+        check_block(P1, "P1");
+        check_same_shape(X, P0, "X", "P0");
+        check_same_shape(X, P1, "X", "P1");
+        AFSI_REQUIRE(X->rows == A->n, "X rows != n");
+        AFSI_REQUIRE(!overlap(X, P0) && !overlap(X, P1) && !overlap(P0, P1),
+                     "X, P0 and P1 must not overlap");
+        AFSI_REQUIRE(ngroups >= 0 && ngroups <= 64, "ngroups must be in 0..64");
+        AFSI_REQUIRE(ngroups == 0 || groups, "groups is NULL");
+        const int eb = elem_bytes(X->dtype);
+        const int E = 16 / eb;
+        AFSI_REQUIRE((X->ld * eb) % 16 == 0 && aligned16(X->ptr) && aligned16(P0->ptr) &&
+                         aligned16(P1->ptr),
+                     "batched step needs 16-byte aligned rows");
+        BatchArgs args;
+        std::memset(&args, 0, sizeof args);
+        std::vector<std::pair<int64_t, int64_t>> ranges;
+        for (int g = 0; g < ngroups; ++g) {
+            const afsi_step_group &G = groups[g];
+            if (!G.active || G.ncols == 0) continue;
+            AFSI_REQUIRE(G.col0 >= 0 && G.ncols > 0 && G.col0 + G.ncols <= X->cols,
+                         "group %d columns out of range", g);
+            AFSI_REQUIRE(G.col0 % E == 0 && G.ncols % E == 0,
+                         "group %d: col0 and ncols must be multiples of %d", g, E);
+            AFSI_REQUIRE(G.src >= 0 && G.src <= 2 && (G.dst == 1 || G.dst == 2) && G.src != G.dst,
+                         "group %d: bad src/dst", g);
+            for (auto &r : ranges)
+                AFSI_REQUIRE(G.col0 + G.ncols <= r.first || r.first + r.second <= G.col0,
+                             "groups overlap");
+            ranges.push_back({G.col0, G.ncols});
+            const int k = args.ngroups++;
+            args.vec0[k] = (int)(G.col0 / E);
+            args.vec1[k] = (int)((G.col0 + G.ncols) / E);
+            args.src[k] = G.src;
+            args.dst[k] = G.dst;
+            args.has_v[k] = G.has_v;
+            args.sigma[k] = G.sigma;
+            args.tau[k] = G.tau;
+            args.alpha[k] = G.alpha;
+        }
+        if (args.ngroups == 0 || A->n == 0) return;
+        DeviceGuard dg(A->device);
+        hipStream_t s = as_stream(stream);
+        const MatView mv = matrix_view(A, X->dtype, s);
+        const int p16 = (int)((X->cols * eb + 15) / 16);
+        const int64_t ldv = X->ld * eb / 16;
+        switch (X->dtype) {
+        case AFSI_R64: clenshaw_r64_batched(mv, X->ptr, P0->ptr, P1->ptr, p16, ldv, args, s); break;
+        case AFSI_R32: clenshaw_r32_batched(mv, X->ptr, P0->ptr, P1->ptr, p16, ldv, args, s); break;
+        case AFSI_C128: clenshaw_c128_batched(mv, X->ptr, P0->ptr, P1->ptr, p16, ldv, args, s); break;
+        case AFSI_C64: clenshaw_c64_batched(mv, X->ptr, P0->ptr, P1->ptr, p16, ldv, args, s); break;
+        }
+        AFSI_HIP(hipGetLastError());
+    });
+}
+
+int afsi_block_inner(const afsi_block *X, const afsi_block *Y, afsi_block *G, void *stream) {
+    return guarded([&] {
+        check_block(X, "X");
+        check_block(Y, "Y");
+        check_block(G, "G");
+        check_fp64(X, "X");
+        AFSI_REQUIRE(X->dtype == Y->dtype && X->dtype == G->dtype, "dtypes differ");
+        AFSI_REQUIRE(X->rows == Y->rows && G->rows == X->cols && G->cols == Y->cols,
+                     "shapes do not match G = X^H Y");
+        AFSI_REQUIRE(!overlap(G, X) && !overlap(G, Y), "G overlaps an input");
+        const int comp = X->dtype == AFSI_C128 ? 2 : 1;
+        (void)comp;
+        inner_dev(X->dtype, X->ptr, X->ld, Y->ptr, Y->ld, X->rows, X->cols, Y->cols,
+                  (double *)G->ptr, G->ld, as_stream(stream));
+    });
+}
+
+int afsi_block_gemm(const afsi_block *X, const afsi_block *M, double beta, afsi_block *Y,
+                    void *stream) {
+    return guarded([&] {
+        check_block(X, "X");
+        check_block(M, "M");
+        check_block(Y, "Y");
+        check_fp64(X, "X");
+        AFSI_REQUIRE(X->dtype == M->dtype && X->dtype == Y->dtype, "dtypes differ");
+        AFSI_REQUIRE(M->rows == X->cols && Y->rows == X->rows && Y->cols == M->cols,
+                     "shapes do not match Y = X M");
+        AFSI_REQUIRE(!overlap(Y, X) && !overlap(Y, M), "Y overlaps an input");
+        gemm_dev(X->dtype, X->ptr, X->ld, (const double *)M->ptr, M->ld, X->rows, X->cols, M->cols,
+                 1.0, beta, Y->ptr, Y->ld, as_stream(stream));
+    });
+}
+
+int afsi_orthonormalize(const afsi_block *locked, afsi_block *X, afsi_block *work, void *stream) {
+    return guarded([&] {
+        check_block(X, "X");
+        check_block(work, "work");
+        check_fp64(X, "X");
+        check_same_shape(X, work, "X", "work");
+        AFSI_REQUIRE(!overlap(X, work), "X and work overlap");
+        AFSI_REQUIRE(X->cols <= X->rows, "more columns than rows");
+        hipStream_t s = as_stream(stream);
+        if (locked && locked->cols > 0) {
+            check_block(locked, "locked");
+            AFSI_REQUIRE(locked->dtype == X->dtype && locked->rows == X->rows, "locked shape/dtype");
+            AFSI_REQUIRE(!overlap(locked, X) && !overlap(locked, work), "locked overlaps X/work");
+            AFSI_REQUIRE(locked->cols + X->cols <= X->rows, "too many columns");
+            project_out_dev(X->dtype, locked->ptr, locked->ld, locked->cols, X->ptr, X->ld, X->rows,
+                            X->cols, s);
+        }
+        orthonormalize_dev(X->dtype, X->ptr, work->ptr, X->rows, X->cols, X->ld, s, nullptr);
+    });
+}
+
+int afsi_rayleigh_ritz(afsi_matrix_t A, const afsi_block *Q, afsi_block *V, afsi_block *AV,
+                       double *ritz_out, void *stream) {
+    return guarded([&] {
+        check_matrix(A);
+        check_block(Q, "Q");
+        check_block(V, "V");
+        check_block(AV, "AV");
+        check_fp64(Q, "Q");
+        check_same_shape(Q, V, "Q", "V");
+        check_same_shape(Q, AV, "Q", "AV");
+        AFSI_REQUIRE(Q->rows == A->n, "Q rows != n");
+        AFSI_REQUIRE(!overlap(Q, V) && !overlap(Q, AV) && !overlap(V, AV), "blocks overlap");
+        AFSI_REQUIRE(ritz_out != nullptr || Q->cols == 0, "ritz_out is NULL");
+        DeviceGuard dg(A->device);
+        rayleigh_ritz_dev(A, Q->dtype, Q->ptr, V->ptr, AV->ptr, Q->rows, Q->cols, Q->ld, ritz_out,
+                          as_stream(stream));
+    });
+}
+
+int afsi_residual_norms(const afsi_block *V, const afsi_block *AV, const double *lambda,
+                        double *norms_out, void *stream) {
+    return guarded([&] {
+        check_block(V, "V");
+        check_block(AV, "AV");
+        check_fp64(V, "V");
+        AFSI_REQUIRE(V->rows == AV->rows && V->cols == AV->cols && V->dtype == AV->dtype,
+                     "V and AV shapes differ");
+        AFSI_REQUIRE(V->cols == 0 || (lambda && norms_out), "NULL lambda / norms_out");
+        residual_norms_host(V->dtype, V->ptr, V->ld, AV->ptr, AV->ld, lambda, V->rows, V->cols,
+                            norms_out, as_stream(stream));
+    });
+}
+
+int afsi_convert_block(const afsi_block *src, afsi_block *dst, void *stream) {
+    return guarded([&] {
+        check_block(src, "src");
+        check_block(dst, "dst");
+        AFSI_REQUIRE(src->rows == dst->rows && src->cols == dst->cols, "shapes differ");
+        AFSI_REQUIRE(is_complex(src->dtype) == is_complex(dst->dtype), "real/complex mismatch");
+        AFSI_REQUIRE(!overlap(src, dst), "src and dst overlap");
+        launch_convert(*src, *dst, as_stream(stream));
+    });
+}
+
+int afsi_gather_columns(const afsi_block *src, const int32_t *cols, int64_t count, afsi_block *dst,
+                        void *stream) {
+    return guarded([&] {
+        check_block(src, "src");
+        check_block(dst, "dst");
+        AFSI_REQUIRE(count >= 0 && dst->cols == count && dst->rows == src->rows &&
+                         dst->dtype == src->dtype,
+                     "dst must be rows x count of src's dtype");
+        AFSI_REQUIRE(count == 0 || cols, "cols is NULL");
+        for (int64_t t = 0; t < count; ++t)
+            AFSI_REQUIRE(cols[t] >= 0 && cols[t] < src->cols, "column index %d out of range", cols[t]);
+        AFSI_REQUIRE(!overlap(src, dst), "src and dst overlap");
+        if (count == 0 || src->rows == 0) return;
+        hipStream_t s = as_stream(stream);
+        Workspace &ws = workspace(s);
+        int32_t *d = (int32_t *)ws.dev_reserve(SLOT_GATHER, sizeof(int32_t) * count);
+        AFSI_HIP(hipMemcpyAsync(d, cols, sizeof(int32_t) * count, hipMemcpyHostToDevice, s));
+        launch_gather_columns(*src, d, count, *dst, s);
+        AFSI_HIP(hipStreamSynchronize(s));
+    });
+}
+
+int afsi_select_degree(const double *ritz, int64_t p, int64_t e, const double *coeffs, int kmax,
+                       double l1, double l2, double tau_a, int *degree_out) {
+    return guarded([&] {
+        AFSI_REQUIRE(ritz && coeffs && degree_out, "NULL argument");
+        AFSI_REQUIRE(kmax >= 1, "kmax must be >= 1");
+        *degree_out = select_degree(ritz, p, e, coeffs, kmax, l1, l2, tau_a);
+    });
+}
+
+int afsi_host_eigh(int64_t p, int32_t dtype, const double *B, int64_t ldb, double *w, double *U,
+                   int64_t ldu) {
+    return guarded([&] {
+        AFSI_REQUIRE(dtype == AFSI_R64 || dtype == AFSI_C128, "dtype must be R64 or C128");
+        AFSI_REQUIRE(p >= 0 && ldb >= p && ldu >= p, "bad shape");
+        AFSI_REQUIRE(p == 0 || (B && w && U), "NULL argument");
+        host_eigh(p, dtype == AFSI_C128, B, ldb, w, U, ldu);
+    });
+}
+
+int afsi_host_cholesky_inverse(int64_t p, int32_t dtype, double *G, int64_t ldg, double shift) {
+    return guarded([&] {
+        AFSI_REQUIRE(dtype == AFSI_R64 || dtype == AFSI_C128, "dtype must be R64 or C128");
+        AFSI_REQUIRE(p >= 0 && ldg >= p && (p == 0 || G), "bad argument");
+        if (!host_cholesky_inverse(p, dtype == AFSI_C128, G, ldg, shift))
+            AFSI_FAIL(AFSI_E_NOT_HPD, "matrix is not positive definite");
+    });
+}
+
+int afsi_lock_select(const double *ritz, int64_t p, const double *res, uint8_t *in_interval,
+                     double a, double b, double tau_abs, int64_t n_lock, int64_t *n_check_prev,
+                     uint8_t *lock, int *done) {
+    return guarded([&] {
+        AFSI_REQUIRE(ritz && res && in_interval && n_check_prev && lock && done, "NULL argument");
+        lock_select(ritz, p, res, in_interval, a, b, tau_abs, n_lock, n_check_prev, lock, done);
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,239 @@
+// Fused Clenshaw step over a CSR matrix and row-major dense blocks (gfx950).
+//
+// One product of Clenshaw's recurrence (Algorithm 2, division-free form):
+//
+//     dst[i, :] = sigma * sum_e A[i, col_e] * src[col_e, :] + tau * src[i, :]
+//                 - dst[i, :]            (HAS_V: the block b_{j+2}, read in place)
+//                 + alpha * X[i, :]      (HAS_X)
+//
+// Mapping: a group of L lanes owns one row; the row's p columns are split into
+// 16-byte vectors and lane `sub` of the group owns vectors v*L + sub, v < VN, so
+// each load instruction of the group reads L*16 contiguous bytes of a row.  The
+// row's (column, value) pairs are the same for every lane of the group (scalar
+// registers when L = 64).  U nonzeros are fetched together so that U*VN row
+// gathers are in flight per lane; the tail of a row is handled by clamping the
+// index and predicating the multiply-add, never by reading past the row.
+// MASKED variants use L = 64 and loop over chunks of 64*VN vectors with a bounds
+// test, for any width.
+#pragma once
+
+#include "vec_types.h"
+
+namespace afsi {
+
+template <class Tr, int VN, int U>
+__device__ inline void gather_accumulate(int start, int end, const int *__restrict__ ci,
+                                         const typename Tr::val *__restrict__ va,
+                                         const typename Tr::vec *__restrict__ src, int64_t ldv,
+                                         int64_t off, int stride, int nvalid,
+                                         typename Tr::vec (&acc)[VN]) {
+    using vec = typename Tr::vec;
+    using val = typename Tr::val;
+    for (int e0 = start; e0 < end; e0 += U) {
+        int c[U];
+        val a[U];
+        bool ok[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            ok[u] = e0 + u < end;
+            const int e = ok[u] ? e0 + u : end - 1;
+            c[u] = ci[e];
+            a[u] = va[e];
+        }
+        vec w[U][VN];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const vec *rowp = src + (int64_t)c[u] * ldv + off;
+#pragma unroll
+            for (int v = 0; v < VN; ++v)
+                if (v < nvalid) w[u][v] = rowp[v * stride];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (ok[u]) {
+#pragma unroll
+                for (int v = 0; v < VN; ++v)
+                    if (v < nvalid) acc[v] = Tr::fma_val(a[u], w[u][v], acc[v]);
+            }
+        }
+    }
+}
+
+template <class Tr, int VN, int L, bool HAS_V, bool HAS_X, int U>
+__global__ __launch_bounds__(256) void clenshaw_step_kernel(
+    int n, const int *__restrict__ rp, const int *__restrict__ ci,
+    const typename Tr::val *__restrict__ va, const typename Tr::vec *__restrict__ src,
+    const typename Tr::vec *__restrict__ X, typename Tr::vec *dst, int64_t ldv,
+    typename Tr::scal sigma, typename Tr::scal tau, typename Tr::scal alpha) {
+    using vec = typename Tr::vec;
+    constexpr int RW = 64 / L;
+    const int lane = threadIdx.x & 63;
+    const int sub = lane % L;
+    int row = (int)(blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6)) * RW + lane / L;
+    if (L == 64) row = __builtin_amdgcn_readfirstlane(row);
+    if (row >= n) return;
+    const int start = rp[row], end = rp[row + 1];
+    vec acc[VN];
+#pragma unroll
+    for (int v = 0; v < VN; ++v) acc[v] = Tr::zero();
+    gather_accumulate<Tr, VN, U>(start, end, ci, va, src, ldv, sub, L, VN, acc);
+    const int64_t base = (int64_t)row * ldv + sub;
+#pragma unroll
+    for (int v = 0; v < VN; ++v) {
+        const int64_t idx = base + v * L;
+        vec r = clenshaw_combine<Tr>(sigma, tau, acc[v], src[idx]);
+        if (HAS_V) r = Tr::sub(r, dst[idx]);
+        if (HAS_X) r = Tr::axpy(alpha, X[idx], r);
+        dst[idx] = r;
+    }
+}
+
+// Any width: L = 64 lanes per row, chunks of 64*VN vectors, bounds-tested.
+template <class Tr, int VN, bool HAS_V, bool HAS_X, int U>
+__global__ __launch_bounds__(256) void clenshaw_step_masked_kernel(
+    int n, const int *__restrict__ rp, const int *__restrict__ ci,
+    const typename Tr::val *__restrict__ va, const typename Tr::vec *__restrict__ src,
+    const typename Tr::vec *__restrict__ X, typename Tr::vec *dst, int64_t ldv, int p16,
+    typename Tr::scal sigma, typename Tr::scal tau, typename Tr::scal alpha) {
+    using vec = typename Tr::vec;
+    const int lane = threadIdx.x & 63;
+    int row = (int)(blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6));
+    row = __builtin_amdgcn_readfirstlane(row);
+    if (row >= n) return;
+    const int start = rp[row], end = rp[row + 1];
+    for (int c0 = 0; c0 < p16; c0 += 64 * VN) {
+        // vectors c0 + v*64 + lane that exist in this row
+        const int left = p16 - c0 - lane;  // > 0 for v = 0 if this lane has any
+        const int nvalid = left <= 0 ? 0 : (left + 63) / 64;
+        vec acc[VN];
+#pragma unroll
+        for (int v = 0; v < VN; ++v) acc[v] = Tr::zero();
+        gather_accumulate<Tr, VN, U>(start, end, ci, va, src, ldv, c0 + lane, 64, nvalid, acc);
+        const int64_t base = (int64_t)row * ldv + c0 + lane;
+#pragma unroll
+        for (int v = 0; v < VN; ++v) {
+            if (v < nvalid) {
+                const int64_t idx = base + v * 64;
+                vec r = clenshaw_combine<Tr>(sigma, tau, acc[v], src[idx]);
+                if (HAS_V) r = Tr::sub(r, dst[idx]);
+                if (HAS_X) r = Tr::axpy(alpha, X[idx], r);
+                dst[idx] = r;
+            }
+        }
+    }
+}
+
+// Unaligned rows: one wave per row, one element per lane per 64 columns.
+template <class Tr, int VN, int U>
+__global__ __launch_bounds__(256) void clenshaw_step_scalar_kernel(
+    int n, const int *__restrict__ rp, const int *__restrict__ ci,
+    const typename Tr::val *__restrict__ va, const typename Tr::vec *__restrict__ src,
+    const typename Tr::vec *__restrict__ X, typename Tr::vec *dst, int64_t ld, int p, int has_v,
+    int has_x, typename Tr::scal sigma, typename Tr::scal tau, typename Tr::scal alpha) {
+    using vec = typename Tr::vec;
+    const int lane = threadIdx.x & 63;
+    int row = (int)(blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6));
+    row = __builtin_amdgcn_readfirstlane(row);
+    if (row >= n) return;
+    const int start = rp[row], end = rp[row + 1];
+    for (int c0 = 0; c0 < p; c0 += 64 * VN) {
+        const int left = p - c0 - lane;
+        const int nvalid = left <= 0 ? 0 : (left + 63) / 64;
+        vec acc[VN];
+#pragma unroll
+        for (int v = 0; v < VN; ++v) acc[v] = Tr::zero();
+        gather_accumulate<Tr, VN, U>(start, end, ci, va, src, ld, c0 + lane, 64, nvalid, acc);
+        const int64_t base = (int64_t)row * ld + c0 + lane;
+#pragma unroll
+        for (int v = 0; v < VN; ++v) {
+            if (v < nvalid) {
+                const int64_t idx = base + v * 64;
+                vec r = clenshaw_combine<Tr>(sigma, tau, acc[v], src[idx]);
+                if (has_v) r = Tr::sub(r, dst[idx]);
+                if (has_x) r = Tr::axpy(alpha, X[idx], r);
+                dst[idx] = r;
+            }
+        }
+    }
+}
+
+// Batched: column groups with their own source block, flags and scalars.
+struct BatchArgs {
+    int ngroups;
+    int vec0[64], vec1[64];   // group g owns row vectors [vec0, vec1)
+    int src[64], dst[64];     // 0 = X, 1 = P0, 2 = P1
+    int has_v[64];
+    double sigma[64], tau[64], alpha[64];
+};
+
+template <class Tr, int VN, int U>
+__global__ __launch_bounds__(256) void clenshaw_batched_kernel(
+    int n, const int *__restrict__ rp, const int *__restrict__ ci,
+    const typename Tr::val *__restrict__ va, const typename Tr::vec *__restrict__ X,
+    typename Tr::vec *P0, typename Tr::vec *P1, int64_t ldv, int p16, const BatchArgs args) {
+    using vec = typename Tr::vec;
+    using scal = typename Tr::scal;
+    const int lane = threadIdx.x & 63;
+    int row = (int)(blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6));
+    row = __builtin_amdgcn_readfirstlane(row);
+    if (row >= n) return;
+    const int start = rp[row], end = rp[row + 1];
+    for (int c0 = 0; c0 < p16; c0 += 64 * VN) {
+        int grp[VN];
+        const vec *sp[VN];
+        int live = 0;
+#pragma unroll
+        for (int v = 0; v < VN; ++v) {
+            const int vi = c0 + v * 64 + lane;
+            grp[v] = -1;
+            for (int g = 0; g < args.ngroups; ++g)
+                if (vi >= args.vec0[g] && vi < args.vec1[g]) grp[v] = g;
+            const int s = grp[v] >= 0 ? args.src[grp[v]] : 0;
+            sp[v] = s == 0 ? X : (s == 1 ? P0 : P1);
+            live |= (grp[v] >= 0) << v;
+        }
+        vec acc[VN];
+#pragma unroll
+        for (int v = 0; v < VN; ++v) acc[v] = Tr::zero();
+        for (int e0 = start; e0 < end; e0 += U) {
+            int c[U];
+            typename Tr::val a[U];
+            bool ok[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                ok[u] = e0 + u < end;
+                const int e = ok[u] ? e0 + u : end - 1;
+                c[u] = ci[e];
+                a[u] = va[e];
+            }
+            vec w[U][VN];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int v = 0; v < VN; ++v)
+                    if (live & (1 << v))
+                        w[u][v] = sp[v][(int64_t)c[u] * ldv + c0 + v * 64 + lane];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (ok[u])
+#pragma unroll
+                    for (int v = 0; v < VN; ++v)
+                        if (live & (1 << v)) acc[v] = Tr::fma_val(a[u], w[u][v], acc[v]);
+        }
+#pragma unroll
+        for (int v = 0; v < VN; ++v) {
+            if (live & (1 << v)) {
+                const int g = grp[v];
+                const int64_t idx = (int64_t)row * ldv + c0 + v * 64 + lane;
+                vec *dp = args.dst[g] == 1 ? P0 : P1;
+                vec r = clenshaw_combine<Tr>((scal)args.sigma[g], (scal)args.tau[g], acc[v],
+                                             sp[v][idx]);
+                if (args.has_v[g]) r = Tr::sub(r, dp[idx]);
+                if (args.alpha[g] != 0.0) r = Tr::axpy((scal)args.alpha[g], X[idx], r);
+                dp[idx] = r;
+            }
+        }
+    }
+}
+
+}  // namespace afsi

@@ -1,0 +1,195 @@
+// Internal declarations shared by the library's translation units (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <mutex>
+#include <string>
+
+#include "../../include/afsi.h"
+
+namespace afsi {
+
+// ---------------------------------------------------------------- errors
+
+void set_error(const char *fmt, ...);
+
+struct Error {
+    int status;
+};
+
+#define AFSI_REQUIRE(cond, ...)                                                                     \
+    do {                                                                                            \
+        if (!(cond)) {                                                                              \
+            ::afsi::set_error(__VA_ARGS__);                                                         \
+            throw ::afsi::Error{AFSI_E_INVALID};                                                    \
+        }                                                                                           \
+    } while (0)
+
+#define AFSI_HIP(expr)                                                                              \
+    do {                                                                                            \
+        hipError_t e_ = (expr);                                                                     \
+        if (e_ != hipSuccess) {                                                                     \
+            ::afsi::set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__,     \
+                              __LINE__);                                                            \
+            throw ::afsi::Error{e_ == hipErrorOutOfMemory ? AFSI_E_NOMEM : AFSI_E_HIP};            \
+        }                                                                                           \
+    } while (0)
+
+#define AFSI_FAIL(status, ...)                                                                      \
+    do {                                                                                            \
+        ::afsi::set_error(__VA_ARGS__);                                                             \
+        throw ::afsi::Error{status};                                                                \
+    } while (0)
+
+// Runs `body` and converts errors into a status code.
+template <class F>
+int guarded(F &&body) {
+    try {
+        body();
+        return AFSI_OK;
+    } catch (const Error &e) {
+        return e.status;
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return AFSI_E_NOMEM;
+    } catch (...) {
+        set_error("unexpected C++ exception");
+        return AFSI_E_HIP;
+    }
+}
+
+// ---------------------------------------------------------------- dtypes
+
+inline int elem_bytes(int dt) {
+    switch (dt) {
+    case AFSI_R64: return 8;
+    case AFSI_R32: return 4;
+    case AFSI_C128: return 16;
+    case AFSI_C64: return 8;
+    }
+    return 0;
+}
+inline bool is_complex(int dt) { return dt == AFSI_C128 || dt == AFSI_C64; }
+inline bool is_fp64(int dt) { return dt == AFSI_R64 || dt == AFSI_C128; }
+
+// ---------------------------------------------------------------- matrix
+
+struct MatView {
+    int64_t n;
+    const int *rp;   // n + 1
+    const int *ci;   // nnz
+    const void *val; // nnz values of the requested precision
+};
+
+}  // namespace afsi
+
+struct afsi_matrix_s {
+    int device = 0;
+    int64_t n = 0, nnz = 0;
+    int32_t dtype = AFSI_R64;  // AFSI_R64 or AFSI_C128
+    int *d_rp = nullptr;
+    int *d_ci = nullptr;
+    void *d_val64 = nullptr;
+    void *d_val32 = nullptr;
+    double lmin = 0, lmax = 0;
+    bool has_bounds = false;
+    std::mutex mu;
+};
+
+namespace afsi {
+
+// Device values matching a block dtype (creates the FP32 copy on first use).
+MatView matrix_view(afsi_matrix_t A, int block_dtype, hipStream_t stream);
+
+// RAII: make `dev` current for the scope.
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev);
+    ~DeviceGuard();
+};
+
+// ---------------------------------------------------------------- scratch
+
+// Per-(device, stream) growable device scratch and pinned host staging.  Slots
+// are independent regions: kernel-internal partial sums (SLOT_PARTIAL), complex
+// real-view temporaries (SLOT_REALVIEW), small matrices of an API call
+// (SLOT_SMALL) and vectors (SLOT_VEC).  Growing a slot synchronises the stream.
+enum { SLOT_PARTIAL = 0, SLOT_REALVIEW = 1, SLOT_SMALL = 2, SLOT_VEC = 3, SLOT_GATHER = 4,
+       NUM_DEV_SLOTS = 5 };
+struct Workspace {
+    hipStream_t stream = nullptr;
+    void *dev[NUM_DEV_SLOTS] = {};
+    size_t dev_bytes[NUM_DEV_SLOTS] = {};
+    void *host[2] = {};
+    size_t host_bytes[2] = {};
+    void *dev_reserve(int slot, size_t bytes);
+    void *host_reserve(int slot, size_t bytes);
+};
+Workspace &workspace(hipStream_t stream);
+
+// ---------------------------------------------------------------- kernels (clenshaw_*.hip)
+
+struct BatchArgs;
+#define AFSI_DECLARE_STEP_ENTRY(NAME)                                                               \
+    void NAME##_step(const MatView &A, const void *src, const void *X, void *dst, int p16,          \
+                     int64_t ldv, bool hv, bool hx, double sg, double ta, double al,               \
+                     hipStream_t s);                                                                \
+    void NAME##_batched(const MatView &A, const void *X, void *P0, void *P1, int p16, int64_t ldv,  \
+                        const BatchArgs &args, hipStream_t s);                                      \
+    void NAME##_scalar(const MatView &A, const void *src, const void *X, void *dst, int p,          \
+                       int64_t ld, bool hv, bool hx, double sg, double ta, double al, hipStream_t s);
+AFSI_DECLARE_STEP_ENTRY(clenshaw_r64)
+AFSI_DECLARE_STEP_ENTRY(clenshaw_r32)
+AFSI_DECLARE_STEP_ENTRY(clenshaw_c128)
+AFSI_DECLARE_STEP_ENTRY(clenshaw_c64)
+
+// ---------------------------------------------------------------- kernels (util.hip)
+
+void launch_convert(const afsi_block &src, const afsi_block &dst, hipStream_t s);
+void launch_gather_columns(const afsi_block &src, const int32_t *d_cols, int64_t count,
+                           const afsi_block &dst, hipStream_t s);
+void launch_to_f32(const double *src, float *dst, int64_t count, hipStream_t s);
+
+// ---------------------------------------------------------------- kernels (dense.hip)
+
+// Real FP64: G (p x q, ldg) = X^T Y; scratch from workspace.
+void gram_f64(const double *X, int64_t ldx, const double *Y, int64_t ldy, int64_t n, int64_t p,
+              int64_t q, double *G, int64_t ldg, hipStream_t s);
+// Real FP64: Y = alpha X M + beta Y.
+void gemm_f64(const double *X, int64_t ldx, const double *M, int64_t ldm, int64_t n, int64_t p,
+              int64_t q, double alpha, double beta, double *Y, int64_t ldy, hipStream_t s);
+// Complex via real views.
+void gram_c128(const double *X, int64_t ldx, const double *Y, int64_t ldy, int64_t n, int64_t p,
+               int64_t q, double *G, int64_t ldg, hipStream_t s);
+void gemm_c128(const double *X, int64_t ldx, const double *M, int64_t ldm, int64_t n, int64_t p,
+               int64_t q, double alpha, double beta, double *Y, int64_t ldy, hipStream_t s);
+// norms[j] = || AV[:, j] - lambda[j] V[:, j] ||_2, device output (q doubles).
+void residual_norms_dev(int dtype, const void *V, int64_t ldv, const void *AV, int64_t ldav,
+                        const double *d_lambda, int64_t n, int64_t q, double *d_norms,
+                        hipStream_t s);
+// ||X||_F^2 per column summed: device scalar.
+void frob2_dev(int dtype, const void *X, int64_t ldx, int64_t n, int64_t q, double *d_out,
+               hipStream_t s);
+
+// ---------------------------------------------------------------- host linear algebra
+
+// Upper Cholesky of a Hermitian p x p matrix (row-major, ld), overwriting with
+// R^{-1} (upper).  Returns false on a non-positive pivot.  Column-scaled.
+bool host_cholesky_inverse(int64_t p, bool cplx, double *G, int64_t ld, double shift);
+// Hermitian eigensolver: w ascending, U (row-major p x p, ldu) unitary eigenvectors.
+void host_eigh(int64_t p, bool cplx, const double *B, int64_t ldb, double *w, double *U,
+               int64_t ldu);
+
+// ---------------------------------------------------------------- coefficients
+
+void filter_coefficients(double lmin, double lmax, double a, double b, int kmax, int damping,
+                         double m_exp, double *coeffs);
+void step_params(const double *coeffs, int degree, int step, double l1, double l2,
+                 afsi_step_group *g);
+int select_degree(const double *ritz, int64_t p, int64_t e, const double *coeffs, int kmax,
+                  double l1, double l2, double tau_a);
+
+}  // namespace afsi

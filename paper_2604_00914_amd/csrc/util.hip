@@ -1,0 +1,94 @@
+// Bandwidth kernels: precision conversion of blocks and matrix values, column gather.
+#include "internal.h"
+
+namespace afsi {
+
+template <class S, class D>
+__global__ void convert_kernel(const S *__restrict__ src, int64_t lds, D *__restrict__ dst,
+                               int64_t ldd, int64_t rows, int64_t cols) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= rows * cols) return;
+    const int64_t i = idx / cols, j = idx % cols;
+    dst[i * ldd + j] = (D)src[i * lds + j];
+}
+
+template <class T>
+__global__ void gather_kernel(const T *__restrict__ src, int64_t lds, const int32_t *__restrict__ cols,
+                              int64_t count, int comp, T *__restrict__ dst, int64_t ldd, int64_t rows) {
+    // comp = scalars per element (1 real, 2 complex)
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t per_row = count * comp;
+    if (idx >= rows * per_row) return;
+    const int64_t i = idx / per_row, r = idx % per_row;
+    const int64_t t = r / comp, c = r % comp;
+    dst[(i * ldd + t) * comp + c] = src[(i * lds + cols[t]) * comp + c];
+}
+
+__global__ void to_f32_kernel(const double *__restrict__ src, float *__restrict__ dst, int64_t count) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < count) dst[idx] = (float)src[idx];
+}
+
+__global__ void scale_strided_kernel(double *__restrict__ x, int64_t n, int64_t ld, int comp,
+                                     double s) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n * comp) return;
+    const int64_t i = idx / comp, c = idx % comp;
+    x[i * ld * comp + c] *= s;
+}
+
+static unsigned blocks_for(int64_t count) { return (unsigned)((count + 255) / 256); }
+
+// x[i * ld + 0..comp) *= s for i < n (one strided column; comp = 2 for complex).
+void launch_scale(double *x, int64_t n, int64_t ld, int comp, double s, hipStream_t st) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(scale_strided_kernel, dim3(blocks_for(n * comp)), dim3(256), 0, st, x, n, ld,
+                       comp, s);
+    AFSI_HIP(hipGetLastError());
+}
+
+void launch_convert(const afsi_block &src, const afsi_block &dst, hipStream_t s) {
+    const int comp = is_complex(src.dtype) ? 2 : 1;
+    const int64_t rows = src.rows, cols = src.cols * comp;
+    const int64_t lds = src.ld * comp, ldd = dst.ld * comp;
+    if (rows * cols == 0) return;
+    const bool s64 = is_fp64(src.dtype), d64 = is_fp64(dst.dtype);
+    const unsigned g = blocks_for(rows * cols);
+    if (s64 && d64)
+        hipLaunchKernelGGL((convert_kernel<double, double>), dim3(g), dim3(256), 0, s,
+                           (const double *)src.ptr, lds, (double *)dst.ptr, ldd, rows, cols);
+    else if (s64 && !d64)
+        hipLaunchKernelGGL((convert_kernel<double, float>), dim3(g), dim3(256), 0, s,
+                           (const double *)src.ptr, lds, (float *)dst.ptr, ldd, rows, cols);
+    else if (!s64 && d64)
+        hipLaunchKernelGGL((convert_kernel<float, double>), dim3(g), dim3(256), 0, s,
+                           (const float *)src.ptr, lds, (double *)dst.ptr, ldd, rows, cols);
+    else
+        hipLaunchKernelGGL((convert_kernel<float, float>), dim3(g), dim3(256), 0, s,
+                           (const float *)src.ptr, lds, (float *)dst.ptr, ldd, rows, cols);
+    AFSI_HIP(hipGetLastError());
+}
+
+void launch_gather_columns(const afsi_block &src, const int32_t *d_cols, int64_t count,
+                           const afsi_block &dst, hipStream_t s) {
+    const int comp = is_complex(src.dtype) ? 2 : 1;
+    const int64_t tot = src.rows * count * comp;
+    if (tot == 0) return;
+    if (is_fp64(src.dtype))
+        hipLaunchKernelGGL((gather_kernel<double>), dim3(blocks_for(tot)), dim3(256), 0, s,
+                           (const double *)src.ptr, src.ld, d_cols, count, comp, (double *)dst.ptr,
+                           dst.ld, src.rows);
+    else
+        hipLaunchKernelGGL((gather_kernel<float>), dim3(blocks_for(tot)), dim3(256), 0, s,
+                           (const float *)src.ptr, src.ld, d_cols, count, comp, (float *)dst.ptr,
+                           dst.ld, src.rows);
+    AFSI_HIP(hipGetLastError());
+}
+
+void launch_to_f32(const double *src, float *dst, int64_t count, hipStream_t s) {
+    if (count == 0) return;
+    hipLaunchKernelGGL(to_f32_kernel, dim3(blocks_for(count)), dim3(256), 0, s, src, dst, count);
+    AFSI_HIP(hipGetLastError());
+}
+
+}  // namespace afsi

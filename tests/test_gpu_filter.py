@@ -1,0 +1,241 @@
+"""GPU parity of the Clenshaw filter (Algorithm 2) against the oracle, through the C ABI.
+
+Tolerances (floating point, derived in the design notes): FP64 blocks agree with
+the FP64 oracle to 1e-12 relative (Frobenius and max-element); FP32 blocks to
+(k+1) * 2^-21 relative, the FP32 rounding of k three-term steps with |sigma A| <= 2.
+"""
+import numpy as np
+import pytest
+
+from oracle import closed_form
+from oracle import coefficients as co
+from oracle.filter import clenshaw_filter
+from paper_2604_00914_amd import afsi
+from tests.gpu_util import DEV, max_rel, rel_fro, to_dev, torch
+from workloads import (
+    build_config,
+    laplacian_3d_dirichlet,
+    random_dense_symmetric_csr,
+    start_block,
+    tight_binding_3d_periodic,
+)
+
+pytestmark = pytest.mark.gpu
+
+F64_TOL = 1e-12
+
+
+def f32_tol(k):
+    return (k + 1) * 2.0 ** -21
+
+
+def _tdt(cplx, single):
+    t = torch()
+    if cplx:
+        return t.complex64 if single else t.complex128
+    return t.float32 if single else t.float64
+
+
+def gpu_filter(A, X0, lmin, lmax, coeffs, degree, single=False, pad=0, offset=0):
+    t = torch()
+    M = afsi.Matrix(A, bounds=(lmin, lmax))
+    n, p = X0.shape
+    dt = _tdt(np.iscomplexobj(X0) or np.iscomplexobj(A.val), single)
+    bufs = [t.zeros((n, p + pad), dtype=dt, device=DEV) for _ in range(3)]
+    X, Y, W = (b[:, offset: offset + p] for b in bufs)
+    X.copy_(t.from_numpy(X0).to(DEV).to(dt))
+    afsi.afsi_filter_block(M.handle, coeffs, degree, X, Y, W)
+    t.cuda.synchronize()
+    out = Y.cpu().numpy().astype(np.complex128 if np.iscomplexobj(X0) else np.float64)
+    M.close()
+    return out
+
+
+def oracle_filter(A, X0, lmin, lmax, a, b, degree, damping="jackson"):
+    c = co.filter_coefficients(lmin, lmax, a, b, degree, damping)
+    l1, l2 = co.affine_map(lmin, lmax)
+    return clenshaw_filter(A, X0, c, l1, l2)
+
+
+def _check(got, ref, tol):
+    assert rel_fro(got, ref) <= tol, rel_fro(got, ref)
+    assert max_rel(got, ref) <= 10 * tol, max_rel(got, ref)
+
+
+def test_config1_full_size_parity():
+    A, (lmin, lmax), (a, b), cfg = build_config("lap2d_64")
+    X0 = start_block(A.n, cfg.p, seed=0)
+    c = afsi.afsi_filter_coefficients(lmin, lmax, a, b, cfg.degree, "jackson")
+    got = gpu_filter(A, X0, lmin, lmax, c, cfg.degree)
+    _check(got, oracle_filter(A, X0, lmin, lmax, a, b, cfg.degree), F64_TOL)
+
+
+_SMALL = random_dense_symmetric_csr(1001, 0.01, seed=9)
+_SMALL_W = (-30.0, 30.0)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 7, 16, 24, 32, 64, 96, 100, 128, 192, 256, 320, 640])
+def test_widths_fp64(p):
+    X0 = start_block(_SMALL.n, p, seed=p)
+    lmin, lmax = _SMALL_W
+    c = afsi.afsi_filter_coefficients(lmin, lmax, -2.0, 3.0, 9, "jackson")
+    got = gpu_filter(_SMALL, X0, lmin, lmax, c, 9)
+    _check(got, oracle_filter(_SMALL, X0, lmin, lmax, -2.0, 3.0, 9), F64_TOL)
+
+
+@pytest.mark.parametrize("p", [1, 3, 4, 8, 64, 160, 256, 640])
+def test_widths_fp32(p):
+    X0 = start_block(_SMALL.n, p, seed=p)
+    lmin, lmax = _SMALL_W
+    k = 9
+    c = afsi.afsi_filter_coefficients(lmin, lmax, -2.0, 3.0, k, "jackson")
+    got = gpu_filter(_SMALL, X0, lmin, lmax, c, k, single=True)
+    ref = oracle_filter(_SMALL, X0, lmin, lmax, -2.0, 3.0, k)
+    assert rel_fro(got, ref) <= f32_tol(k)
+
+
+@pytest.mark.parametrize("single", [False, True])
+@pytest.mark.parametrize("p", [1, 3, 8, 64, 192])
+def test_complex_widths(p, single):
+    A = tight_binding_3d_periodic(6, seed=3)
+    X0 = start_block(A.n, p, seed=p, complex_=True)
+    lmin, lmax = -7.0, 7.0
+    k = 31  # odd degree with a symmetric interval: every odd coefficient is zero
+    c = afsi.afsi_filter_coefficients(lmin, lmax, -0.4, 0.4, k, "jackson")
+    got = gpu_filter(A, X0, lmin, lmax, c, k, single=single)
+    ref = oracle_filter(A, X0, lmin, lmax, -0.4, 0.4, k)
+    if single:
+        assert rel_fro(got, ref) <= f32_tol(k)
+    else:
+        _check(got, ref, F64_TOL)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("symmetric", [False, True])
+def test_low_degrees(k, symmetric):
+    A = laplacian_3d_dirichlet(7, 2.0, seed=1)
+    lmin, lmax = 0.0, 14.0
+    a, b = (6.5, 7.5) if symmetric else (2.0, 3.1)
+    X0 = start_block(A.n, 16, seed=k)
+    c = afsi.afsi_filter_coefficients(lmin, lmax, a, b, k, "lanczos", 0.5)
+    got = gpu_filter(A, X0, lmin, lmax, c, k)
+    _check(got, oracle_filter(A, X0, lmin, lmax, a, b, k, "lanczos"), F64_TOL)
+
+
+@pytest.mark.parametrize("pad,offset", [(8, 0), (5, 3), (1, 1), (64, 32)])
+@pytest.mark.parametrize("p", [2, 64, 100])
+def test_strided_and_unaligned_views(p, pad, offset):
+    A = laplacian_3d_dirichlet(8, 2.0, seed=2)
+    X0 = start_block(A.n, p, seed=1)
+    c = afsi.afsi_filter_coefficients(0.0, 14.0, 4.0, 5.0, 12, "jackson")
+    got = gpu_filter(A, X0, 0.0, 14.0, c, 12, pad=pad, offset=offset)
+    _check(got, oracle_filter(A, X0, 0.0, 14.0, 4.0, 5.0, 12), F64_TOL)
+
+
+def test_untouched_neighbour_columns():
+    # columns outside a view must keep their contents (no vector over-write)
+    t = torch()
+    A = laplacian_3d_dirichlet(5, 0.0)
+    M = afsi.Matrix(A, bounds=(0.0, 12.0))
+    c = afsi.afsi_filter_coefficients(0.0, 12.0, 2.0, 3.0, 6, "jackson")
+    bufs = [t.full((A.n, 9), 7.0, dtype=t.float64, device=DEV) for _ in range(3)]
+    X, Y, W = (bb[:, 1:4] for bb in bufs)
+    X.copy_(to_dev(start_block(A.n, 3, 0)))
+    afsi.afsi_filter_block(M.handle, c, 6, X, Y, W)
+    t.cuda.synchronize()
+    for bb in bufs[1:]:
+        assert bool((bb[:, 0] == 7.0).all()) and bool((bb[:, 4:] == 7.0).all())
+    M.close()
+
+
+def test_ragged_and_degenerate_matrices():
+    # n = 1, rows without entries, an all-zero matrix
+    from workloads import CSR
+
+    for A in [
+        CSR(1, np.array([0, 1]), np.array([0], np.int32), np.array([2.0])),
+        CSR(5, np.array([0, 0, 2, 2, 3, 3]), np.array([1, 3, 3], np.int32), np.array([1.0, 2.0, 3.0])),
+        CSR(6, np.zeros(7, np.int64), np.zeros(0, np.int32), np.zeros(0)),
+    ]:
+        X0 = start_block(A.n, 6, seed=2)
+        c = afsi.afsi_filter_coefficients(-4.0, 4.0, -1.0, 1.5, 5, "jackson")
+        got = gpu_filter(A, X0, -4.0, 4.0, c, 5)
+        _check(got, oracle_filter(A, X0, -4.0, 4.0, -1.0, 1.5, 5), F64_TOL)
+
+
+def test_repeatable_bitwise():
+    A, (lmin, lmax), (a, b), cfg = build_config("lap2d_64")
+    X0 = start_block(A.n, cfg.p, seed=3)
+    c = afsi.afsi_filter_coefficients(lmin, lmax, a, b, cfg.degree, "jackson")
+    y1 = gpu_filter(A, X0, lmin, lmax, c, cfg.degree)
+    y2 = gpu_filter(A, X0, lmin, lmax, c, cfg.degree)
+    assert np.array_equal(y1, y2)
+
+
+def test_batched_groups_bitwise_equal_to_single_filters():
+    t = torch()
+    A = laplacian_3d_dirichlet(10, 2.0, seed=4)
+    lmin, lmax = 0.0, 14.0
+    l1, l2 = co.affine_map(lmin, lmax)
+    groups = [(0, 32, 7, (3.0, 3.5), 0), (32, 64, 12, (5.0, 5.3), 2), (96, 8, 5, (9.0, 11.0), 4)]
+    ptot = 104
+    X0 = start_block(A.n, ptot, seed=5)
+    M = afsi.Matrix(A, bounds=(lmin, lmax))
+    X = to_dev(X0)
+    P0 = t.zeros_like(X)
+    P1 = t.zeros_like(X)
+    coeffs = {g: afsi.afsi_filter_coefficients(lmin, lmax, iv[0], iv[1], k, "jackson") for g, (c0, nc, k, iv, st) in enumerate(groups)}
+    total = max(st + k for (c0, nc, k, iv, st) in groups)
+    for step in range(total):
+        gs = []
+        for g, (c0, nc, k, iv, st) in enumerate(groups):
+            s = step - st
+            if 0 <= s < k:
+                gs.append(afsi.afsi_clenshaw_step_params(coeffs[g], k, s, l1, l2, col0=c0, ncols=nc))
+        afsi.afsi_clenshaw_step_batched(M.handle, gs, X, P0, P1)
+    t.cuda.synchronize()
+    for g, (c0, nc, k, iv, st) in enumerate(groups):
+        Yb = (P0 if (k - 1) % 2 == 0 else P1)[:, c0:c0 + nc].cpu().numpy()
+        Xs = to_dev(X0[:, c0:c0 + nc])
+        Ys, Ws = t.empty_like(Xs), t.empty_like(Xs)
+        afsi.afsi_filter_block(M.handle, coeffs[g], k, Xs, Ys, Ws)
+        t.cuda.synchronize()
+        assert np.array_equal(Yb, Ys.cpu().numpy()), g
+        ref = oracle_filter(A, X0[:, c0:c0 + nc], lmin, lmax, iv[0], iv[1], k)
+        _check(Yb, ref, F64_TOL)
+    M.close()
+
+
+def test_full_size_config2_closed_form_modes():
+    # 100^3 Dirichlet Laplacian (no potential): 256 closed-form eigenvectors map to rho(lambda) v
+    t = torch()
+    N = 100
+    A = laplacian_3d_dirichlet(N, 0.0)
+    lmin, lmax = 0.0, 12.0
+    k, p = 120, 256
+    rng = np.random.default_rng(0)
+    idx = rng.integers(1, N + 1, size=(p, 3))
+    lams = np.array([closed_form.lap3d_mode(N, *m)[0] for m in idx])
+    mid = float(np.median(lams))
+    a, b = mid - 0.3, mid + 0.3
+    c = afsi.afsi_filter_coefficients(lmin, lmax, a, b, k, "jackson")
+    X = t.empty((A.n, p), dtype=t.float64, device=DEV)
+    for j, m in enumerate(idx):
+        X[:, j] = to_dev(closed_form.lap3d_mode(N, *m)[1])
+    M = afsi.Matrix(A, bounds=(lmin, lmax))
+    Y, W = t.empty_like(X), t.empty_like(X)
+    afsi.afsi_filter_block(M.handle, c, k, X, Y, W)
+    rho = t.from_numpy(co.filter_value(lams, co.filter_coefficients(lmin, lmax, a, b, k, "jackson"), lmin, lmax)).to(DEV)
+    err = (Y - X * rho[None, :]).abs().max().item()
+    assert err < 1e-12, err
+    M.close()
+
+
+def test_full_size_config2_low_degree_vs_oracle():
+    # the production shape (n = 1e6, p = 256, FP64) at degree 3 against the full oracle
+    A, (lmin, lmax), (a, b), cfg = build_config("lap3d_pot_100")
+    X0 = start_block(A.n, cfg.p, seed=0)
+    c = afsi.afsi_filter_coefficients(lmin, lmax, a, b, 3, "jackson")
+    got = gpu_filter(A, X0, lmin, lmax, c, 3)
+    ref = oracle_filter(A, X0, lmin, lmax, a, b, 3)
+    _check(got, ref, F64_TOL)

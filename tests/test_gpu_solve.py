@@ -1,0 +1,139 @@
+"""End-to-end parity of the GPU solver (Algorithm 4) against closed forms, dense
+brute force and the oracle.
+
+FP64 form: eigenvalues within 1e-10 ||A||, residuals ||Av - lambda v|| <= 1e-9 ||A||,
+exact counts.  Mixed form (FP32 filter, FP64 projections; locking at 1e-6 ||A||):
+eigenvalues within 1e-5 relative (to ||A||) and residuals <= 1e-5 ||A||.
+"""
+import numpy as np
+import pytest
+
+from oracle import closed_form
+from oracle import solver as osolver
+from paper_2604_00914_amd import afsi
+from tests.gpu_util import DEV, to_dev, torch
+from workloads import (
+    build_config,
+    laplacian_3d_dirichlet,
+    random_banded_symmetric,
+    start_block,
+    tight_binding_3d_periodic,
+)
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu_solve(A, a, b, lmin, lmax, X0, kmax, mixed=False, adaptive=False, damping="jackson",
+              tau_c=None, max_iter=400, capacity=None):
+    t = torch()
+    M = afsi.Matrix(A, bounds=(lmin, lmax))
+    cplx = A.is_complex
+    o = afsi.afsi_options_default(kmax)
+    o.max_iter = max_iter
+    o.adaptive = int(adaptive)
+    o.damping = {"jackson": 1, "lanczos": 2, "none": 0}[damping]
+    if mixed:
+        o.filter_dtype = afsi.C64 if cplx else afsi.R32
+        o.tau_c = 1e-6
+    else:
+        o.filter_dtype = afsi.C128 if cplx else afsi.R64
+    if tau_c is not None:
+        o.tau_c = tau_c
+    X = to_dev(X0)
+    cap = capacity or X0.shape[1]
+    E = t.zeros((A.n, cap), dtype=X.dtype, device=DEV)
+    st, lam, res, r = afsi.afsi_solve(M.handle, a, b, o, X, E, cap)
+    V = E[:, : r.count].cpu().numpy()
+    M.close()
+    return st, lam, res, r, V
+
+
+def _check_pairs(A, lam, V, ref, normA, ev_tol, res_tol):
+    assert lam.size == ref.size
+    assert np.max(np.abs(lam - ref)) <= ev_tol * normA, np.max(np.abs(lam - ref))
+    R = A.to_scipy() @ V - V * lam
+    assert np.max(np.linalg.norm(R, axis=0)) <= res_tol * normA
+    G = V.conj().T @ V
+    assert np.max(np.abs(G - np.eye(lam.size))) < 1e-8
+
+
+def test_config1_fp64_closed_form_and_oracle():
+    A, (lmin, lmax), (a, b), cfg = build_config("lap2d_64")
+    exact = closed_form.lap2d_eigs(64)
+    exact = exact[(exact >= a) & (exact <= b)]
+    X0 = start_block(A.n, cfg.p, seed=0)
+    st, lam, res, r, V = gpu_solve(A, a, b, lmin, lmax, X0, cfg.degree)
+    normA = max(abs(lmin), abs(lmax))
+    assert st == 0 and r.converged and r.count == 40
+    _check_pairs(A, lam, V, exact, normA, 1e-10, 1e-9)
+    o = osolver.solve(A, a, b, lmin, lmax, X0, osolver.Options(kmax=cfg.degree))
+    assert np.max(np.abs(lam - o.eigenvalues)) <= 1e-10 * normA
+    assert np.all(res <= 1e-10 * normA)
+
+
+def test_config1_mixed_precision():
+    A, (lmin, lmax), (a, b), cfg = build_config("lap2d_64")
+    exact = closed_form.lap2d_eigs(64)
+    exact = exact[(exact >= a) & (exact <= b)]
+    X0 = start_block(A.n, cfg.p, seed=1)
+    st, lam, res, r, V = gpu_solve(A, a, b, lmin, lmax, X0, cfg.degree, mixed=True)
+    normA = max(abs(lmin), abs(lmax))
+    assert st == 0 and r.count == 40
+    _check_pairs(A, lam, V, exact, normA, 1e-5, 1e-5)
+
+
+def _bf(A, count, p, kmax, seed, **kw):
+    w = np.linalg.eigvalsh(A.to_dense())
+    lo = A.n // 2 - count // 2
+    a = 0.5 * (w[lo - 1] + w[lo])
+    b = 0.5 * (w[lo + count - 1] + w[lo + count])
+    lmin, lmax = w[0] - 1e-2, w[-1] + 1e-2
+    X0 = start_block(A.n, p, seed=seed, complex_=A.is_complex)
+    st, lam, res, r, V = gpu_solve(A, a, b, lmin, lmax, X0, kmax, **kw)
+    return st, lam, V, r, w[lo: lo + count], max(abs(lmin), abs(lmax))
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+@pytest.mark.parametrize("case", ["lap3d", "tb", "rand"])
+def test_brute_force_tiers(case, mixed):
+    A = {
+        "lap3d": lambda: laplacian_3d_dirichlet(12, 2.0, seed=1),
+        "tb": lambda: tight_binding_3d_periodic(12, seed=1),
+        "rand": lambda: random_banded_symmetric(2000, seed=1, band=16),
+    }[case]()
+    count = 12 if case == "rand" else 16
+    st, lam, V, r, ref, normA = _bf(A, count, 48, 200, 0, mixed=mixed)
+    assert st == 0 and r.count == count
+    tol = (1e-5, 1e-5) if mixed else (1e-10, 1e-9)
+    _check_pairs(A, lam, V, ref, normA, *tol)
+
+
+def test_adaptive_lanczos_mode():
+    A = laplacian_3d_dirichlet(12, 2.0, seed=3)
+    st, lam, V, r, ref, normA = _bf(A, 16, 32, 300, 0, adaptive=True, damping="lanczos")
+    assert st == 0 and r.count == 16 and r.avg_degree < 300
+    _check_pairs(A, lam, V, ref, normA, 1e-10, 1e-9)
+
+
+def test_iteration_limit_returns_partial():
+    A, (lmin, lmax), (a, b), cfg = build_config("lap2d_64")
+    st, lam, res, r, V = gpu_solve(A, a, b, lmin, lmax, start_block(A.n, 64, 0), 60, max_iter=2)
+    assert st == -6 and not r.converged and r.iterations == 2
+
+
+def test_bounds_too_narrow_are_detected():
+    A, (lmin, lmax), (a, b), cfg = build_config("lap2d_64")
+    with pytest.raises(afsi.AfsiError) as e:
+        gpu_solve(A, a, b, 0.0, 4.0, start_block(A.n, 64, 0), 60, max_iter=3)
+    assert e.value.status in (-5, -4)
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_lanczos_bounds_enclose_spectrum(cplx):
+    A = tight_binding_3d_periodic(8, seed=4) if cplx else laplacian_3d_dirichlet(8, 2.0, seed=4)
+    w = np.linalg.eigvalsh(A.to_dense())
+    M = afsi.Matrix(A)
+    lo, hi = afsi.afsi_estimate_spectral_bounds(M.handle, 60, 0)
+    assert lo <= w[0] and hi >= w[-1] and hi - lo < 1.2 * (w[-1] - w[0])
+    assert afsi.afsi_get_spectral_bounds(M.handle) == (lo, hi)
+    M.close()
