@@ -19,7 +19,7 @@ namespace afsi {
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 // MFMA 16x16x4 f64 operand layout: lane l holds A[l % 16][l / 16] and B[l / 16][l % 16];
-// accumulator element e of lane l is D[4 (l / 16) + e][l % 16].
+// accumulator element e of lane l is D[l / 16 + 4 e][l % 16] (rows interleaved by 4).
 __device__ inline d4 mfma16x16x4(double a, double b, d4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
@@ -59,12 +59,12 @@ __global__ __launch_bounds__(256) void gram_f64_kernel(const double *__restrict_
     const d4 accs[4] = {acc00, acc01, acc10, acc11};
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-        const int gi0 = i0 + (t >> 1) * 16 + 4 * lk;
+        const int gi0 = i0 + (t >> 1) * 16 + lk;
         const int gj = j0 + (t & 1) * 16 + lc;
         if (gj >= q) continue;
 #pragma unroll
         for (int e = 0; e < 4; ++e)
-            if (gi0 + e < p) out[(int64_t)(gi0 + e) * q + gj] = accs[t][e];
+            if (gi0 + 4 * e < p) out[(int64_t)(gi0 + 4 * e) * q + gj] = accs[t][e];
     }
 }
 
@@ -110,12 +110,12 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const double *__restrict_
     const d4 accs[4] = {acc00, acc01, acc10, acc11};
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-        const int64_t gi0 = r0 + (t >> 1) * 16 + 4 * lk;
+        const int64_t gi0 = r0 + (t >> 1) * 16 + lk;
         const int gj = c0 + (t & 1) * 16 + lc;
         if (gj >= q) continue;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            const int64_t gi = gi0 + e;
+            const int64_t gi = gi0 + 4 * e;
             if (gi < n) {
                 double *yp = Y + gi * ldy + gj;
                 double v = alpha * accs[t][e];
