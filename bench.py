@@ -33,6 +33,17 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def kernel_source_sha1():
+    """Hash of the Clenshaw kernel sources (ties stored counter data to the kernel it measured)."""
+    import hashlib
+
+    h = hashlib.sha1()
+    csrc = os.path.join(ROOT, "paper_2604_00914_amd", "csrc")
+    for f in ("vec_types.h", "clenshaw_kernels.h", "clenshaw_dispatch.h"):
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()
+
+
 def filter_bytes(nnz, n, p, sx, sval, coeffs, degree):
     """Algorithmic (compulsory) bytes of one filter application and of one steady launch.
 
@@ -67,6 +78,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run three plain device copies of one block (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -103,6 +116,13 @@ def main():
         F0 = torch.empty((n, p), dtype=f32, device=dev)
         F1, F2 = torch.empty_like(F0), torch.empty_like(F0)
     stream = torch.cuda.current_stream()
+    if args.calibrate_copy:
+        # a plain device copy of one n x p block: reference for the HBM byte counters
+        for _ in range(3):
+            B1.copy_(B0)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": B0.numel() * B0.element_size()}), flush=True)
+        return
     afsi.afsi_orthonormalize(None, B0, B1)
     torch.cuda.synchronize()
 
@@ -110,20 +130,23 @@ def main():
     sval = sx  # the matrix values are read in the filter's precision
     fbytes, steady_bytes = filter_bytes(A.nnz, n, p, sx, sval, coeffs, k)
 
+    # every product of the filter is bracketed by HIP events on this stream
+    steady_ms = []   # products that gather src, read V in place and read X (the dominant kernel)
+
     def run_filter(deg):
         if args.form == "fp64":
-            afsi.afsi_filter_block(M.handle, coeffs, deg, B0, B1, B2)
+            ms, kind = afsi.afsi_filter_block_profiled(M.handle, coeffs, deg, B0, B1, B2)
         else:
             afsi.afsi_convert_block(B0, F0)
-            afsi.afsi_filter_block(M.handle, coeffs, deg, F0, F1, F2)
+            ms, kind = afsi.afsi_filter_block_profiled(M.handle, coeffs, deg, F0, F1, F2)
             afsi.afsi_convert_block(F1, B1)
+        steady_ms.extend(ms[2:][kind[2:] == 3].tolist())
 
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     filt_ms = []
     n_check = [0]
 
     def step():
-        nonlocal B0, B1, B2
         ev[0].record(stream)
         run_filter(k)
         ev[1].record(stream)
@@ -136,19 +159,10 @@ def main():
             _, _, _, n_check[0] = afsi.afsi_lock_select(ritz, res, inside, a, b, 1e-10 * normA, 0, n_check[0])
         filt_ms.append(ev[0].elapsed_time(ev[1]))
 
-    # degree-2 filters time the first two (special) products, so that the
-    # steady-state kernel's per-launch time is (t_k - t_2) / (k - 2)
-    t2 = []
     for w in range(max(args.warmup, 1)):
         step()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        for _ in range(3):
-            e0.record(stream)
-            run_filter(2)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            t2.append(e0.elapsed_time(e1))
     filt_ms.clear()
+    steady_ms.clear()
     torch.cuda.synchronize()
     log(f"warmup done; timing {args.steps} steps")
     tstart = time.perf_counter()
@@ -158,18 +172,21 @@ def main():
     elapsed = time.perf_counter() - tstart
     ms_per_step = 1e3 * elapsed / args.steps
     value = fbytes * args.steps / elapsed / 1e9
-    t2_med = float(np.median(t2))
     filt_med = float(np.median(filt_ms))
-    steady_launch_ms = (filt_med - t2_med) / (k - 2)
+    steady_launch_ms = float(np.mean(steady_ms))
     achieved = steady_bytes / (steady_launch_ms * 1e-3) / 1e9
     filter_gbs = fbytes / (filt_med * 1e-3) / 1e9
     log(f"step {ms_per_step:.2f} ms, filter {filt_med:.2f} ms ({filter_gbs:.0f} GB/s), "
-        f"steady launch {steady_launch_ms * 1e3:.1f} us ({achieved:.0f} GB/s)")
+        f"dominant kernel {steady_launch_ms * 1e3:.1f} us avg over {len(steady_ms)} launches ({achieved:.0f} GB/s)")
 
     traffic = None
     tpath = os.path.join(ROOT, "profiles", f"traffic_{cfg.name}_{args.form}.json")
     if os.path.exists(tpath):
-        traffic = json.load(open(tpath)).get("hbm_bytes_per_launch")
+        rec = json.load(open(tpath))
+        if rec.get("kernel_source_sha1") == kernel_source_sha1():
+            traffic = rec.get("hbm_bytes_per_launch")
+        else:
+            log("stored HBM traffic was taken for other kernel sources: reporting traffic = null")
 
     out = {
         "metric": "SpMM-filter GB/s (% HBM peak); eigenpairs/s mixed vs FP64; p99 latency",
@@ -194,7 +211,8 @@ def main():
         "filter_only_gbs": round(filter_gbs, 1),
         "filter_ms": round(filt_med, 3),
         "roofline": {
-            "kernel": "clenshaw_step_kernel (steady state: gather src, read V in place, read X, write V)",
+            "kernel": "clenshaw_step_kernel<HAS_V=1,HAS_X=1> (gather src, read V in place, read X, write V)",
+            "launches": len(steady_ms),
             "bound": "hbm",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,

@@ -136,6 +136,17 @@ int afsi_filter_coefficients(double lmin, double lmax, double a, double b, int k
 int afsi_filter_block(afsi_matrix_t A, const double *coeffs, int degree, const afsi_block *X,
                       afsi_block *Y, afsi_block *work, void *stream);
 
+/*
+ * afsi_filter_block with a HIP event recorded on `stream` before each product
+ * and after the last (per-kernel timing without a profiler).  step_ms[degree]
+ * (host) receives each product's duration; step_kind[degree] (host, may be NULL)
+ * receives bit 0 = reads the previous block in place, bit 1 = adds the alpha X
+ * term.  Synchronises `stream`.
+ */
+int afsi_filter_block_profiled(afsi_matrix_t A, const double *coeffs, int degree,
+                               const afsi_block *X, afsi_block *Y, afsi_block *work, void *stream,
+                               float *step_ms, int32_t *step_kind);
+
 /* Y = A X (one sparse x dense-block product). X and Y as for afsi_filter_block. */
 int afsi_spmm(afsi_matrix_t A, const afsi_block *X, afsi_block *Y, void *stream);
 

@@ -73,6 +73,7 @@ _SIGS = {
     "afsi_estimate_spectral_bounds": (C.c_int, [_P, C.c_int, C.c_uint64, _P, _DP, _DP]),
     "afsi_filter_coefficients": (C.c_int, [C.c_double, C.c_double, C.c_double, C.c_double, C.c_int, C.c_int32, C.c_double, _P]),
     "afsi_filter_block": (C.c_int, [_P, _P, C.c_int, _BP, _BP, _BP, _P]),
+    "afsi_filter_block_profiled": (C.c_int, [_P, _P, C.c_int, _BP, _BP, _BP, _P, _P, _P]),
     "afsi_spmm": (C.c_int, [_P, _BP, _BP, _P]),
     "afsi_clenshaw_step_params": (C.c_int, [_P, C.c_int, C.c_int, C.c_double, C.c_double, C.POINTER(afsi_step_group)]),
     "afsi_clenshaw_step_batched": (C.c_int, [_P, C.c_int, C.POINTER(afsi_step_group), _BP, _BP, _BP, _P]),
@@ -216,6 +217,16 @@ def afsi_filter_coefficients(lmin, lmax, a, b, kmax, damping="jackson", m_exp=0.
 def afsi_filter_block(h, coeffs, degree: int, X, Y, work, stream=None):
     c = _np(coeffs, np.float64)
     _check(lib().afsi_filter_block(h, _ptr(c), degree, _bref(_blk(X)), _bref(_blk(Y)), _bref(_blk(work)), _stream(stream)))
+
+
+def afsi_filter_block_profiled(h, coeffs, degree: int, X, Y, work, stream=None):
+    """Returns (step_ms[degree], step_kind[degree]); kind bit 0 = in-place V, bit 1 = X term."""
+    c = _np(coeffs, np.float64)
+    ms = np.zeros(degree, dtype=np.float32)
+    kind = np.zeros(degree, dtype=np.int32)
+    _check(lib().afsi_filter_block_profiled(h, _ptr(c), degree, _bref(_blk(X)), _bref(_blk(Y)), _bref(_blk(work)),
+                                            _stream(stream), _ptr(ms), _ptr(kind)))
+    return ms, kind
 
 
 def afsi_spmm(h, X, Y, stream=None):

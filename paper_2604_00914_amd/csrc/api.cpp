@@ -185,9 +185,12 @@ static void map_coeffs(const afsi_matrix_s *A, double &l1, double &l2) {
 
 static void check_matrix(afsi_matrix_t A) { AFSI_REQUIRE(A != nullptr, "matrix handle is NULL"); }
 
-// Filter on raw pointers (shared by afsi_filter_block and the solver).
+// Filter on raw pointers (shared by afsi_filter_block and the solver).  When
+// `events` is given (degree + 1 events), one is recorded before every product
+// and one after the last; `kind[s]` gets has_v | has_x << 1 of product s.
 void filter_apply(afsi_matrix_t A, const double *coeffs, int degree, int dtype, const void *X,
-                  void *Y, void *work, int64_t p, int64_t ld, hipStream_t s) {
+                  void *Y, void *work, int64_t p, int64_t ld, hipStream_t s, hipEvent_t *events,
+                  int32_t *kind) {
     double l1, l2;
     map_coeffs(A, l1, l2);
     AFSI_REQUIRE(degree >= 1, "degree must be >= 1 (got %d)", degree);
@@ -198,9 +201,12 @@ void filter_apply(afsi_matrix_t A, const double *coeffs, int degree, int dtype, 
     for (int st = 0; st < degree; ++st) {
         afsi_step_group g;
         step_params(coeffs, degree, st, l1, l2, &g);
+        if (events) AFSI_HIP(hipEventRecord(events[st], s));
+        if (kind) kind[st] = (g.has_v ? 1 : 0) | (g.alpha != 0.0 ? 2 : 0);
         run_step(mv, dtype, P[g.src], X, P[g.dst], p, ld, g.has_v != 0, g.alpha != 0.0, g.sigma,
                  g.tau, g.alpha, s);
     }
+    if (events) AFSI_HIP(hipEventRecord(events[degree], s));
 }
 
 void spmm_apply(afsi_matrix_t A, int dtype, const void *X, void *Y, int64_t p, int64_t ld,
@@ -499,6 +505,40 @@ int afsi_filter_block(afsi_matrix_t A, const double *coeffs, int degree, const a
         filter_apply(A, coeffs, degree, X->dtype, X->ptr, Y->ptr, work->ptr, X->cols, X->ld,
                      as_stream(stream));
     });
+}
+
+int afsi_filter_block_profiled(afsi_matrix_t A, const double *coeffs, int degree,
+                               const afsi_block *X, afsi_block *Y, afsi_block *work, void *stream,
+                               float *step_ms, int32_t *step_kind) {
+    std::vector<hipEvent_t> ev;
+    const int status = guarded([&] {
+        check_matrix(A);
+        AFSI_REQUIRE(coeffs != nullptr && step_ms != nullptr, "NULL argument");
+        check_block(X, "X");
+        check_block(Y, "Y");
+        check_block(work, "work");
+        check_same_shape(X, Y, "X", "Y");
+        check_same_shape(X, work, "X", "work");
+        AFSI_REQUIRE(X->rows == A->n, "X rows != n");
+        AFSI_REQUIRE(!overlap(X, Y) && !overlap(X, work) && !overlap(Y, work),
+                     "X, Y and work must not overlap");
+        AFSI_REQUIRE(degree >= 1, "degree must be >= 1");
+        DeviceGuard dg(A->device);
+        hipStream_t s = as_stream(stream);
+        ev.resize(degree + 1, nullptr);
+        for (auto &e : ev) AFSI_HIP(hipEventCreate(&e));
+        std::vector<int32_t> kind(degree);
+        filter_apply(A, coeffs, degree, X->dtype, X->ptr, Y->ptr, work->ptr, X->cols, X->ld, s,
+                     ev.data(), kind.data());
+        AFSI_HIP(hipEventSynchronize(ev[degree]));
+        for (int i = 0; i < degree; ++i) {
+            AFSI_HIP(hipEventElapsedTime(&step_ms[i], ev[i], ev[i + 1]));
+            if (step_kind) step_kind[i] = kind[i];
+        }
+    });
+    for (auto &e : ev)
+        if (e) (void)hipEventDestroy(e);
+    return status;
 }
 
 int afsi_spmm(afsi_matrix_t A, const afsi_block *X, afsi_block *Y, void *stream) {

@@ -1,23 +1,42 @@
 // Host-side choice of the Clenshaw-step kernel variant for one element type.
 #pragma once
 
+#include <algorithm>
+
 #include "clenshaw_kernels.h"
 #include "internal.h"
 
 namespace afsi {
+
+// XCD-aware grid: every XCD processes runs of `group` consecutive workgroups,
+// about 4096 rows, and the grid is padded to a multiple of 8 * group.
+struct Grid {
+    int group;
+    int nblocks;
+    int64_t grid;
+};
+inline Grid xcd_grid(int64_t n, int rows_per_block) {
+    Grid g;
+    g.nblocks = (int)((n + rows_per_block - 1) / rows_per_block);
+    int grp = std::max(1, 4096 / rows_per_block);
+    const int per_xcd = (g.nblocks + 7) / 8;
+    grp = std::min(grp, std::max(1, per_xcd));
+    g.group = grp;
+    g.grid = grp <= 1 ? g.nblocks : ((int64_t)g.nblocks + 8 * grp - 1) / (8 * grp) * (8 * grp);
+    return g;
+}
 
 template <class Tr, int VN, int L, bool HV, bool HX>
 void launch_exact(const MatView &A, const void *src, const void *X, void *dst, int64_t ldv,
                   double sigma, double tau, double alpha, hipStream_t s) {
     using vec = typename Tr::vec;
     using scal = typename Tr::scal;
-    constexpr int U = VN <= 2 ? 8 : (VN <= 4 ? 4 : 2);
-    constexpr int rows_per_block = 4 * (64 / L);
-    const int64_t grid = (A.n + rows_per_block - 1) / rows_per_block;
-    hipLaunchKernelGGL((clenshaw_step_kernel<Tr, VN, L, HV, HX, U>), dim3((unsigned)grid), dim3(256),
-                       0, s, (int)A.n, A.rp, A.ci, (const typename Tr::val *)A.val,
+    constexpr int U = VN <= 4 ? 8 : 4;
+    const Grid g = xcd_grid(A.n, 4 * (64 / L));
+    hipLaunchKernelGGL((clenshaw_step_kernel<Tr, VN, L, HV, HX, U>), dim3((unsigned)g.grid),
+                       dim3(256), 0, s, (int)A.n, A.rp, A.ci, (const typename Tr::val *)A.val,
                        (const vec *)src, (const vec *)X, (vec *)dst, ldv, (scal)sigma, (scal)tau,
-                       (scal)alpha);
+                       (scal)alpha, g.group, g.nblocks);
 }
 
 template <class Tr, int VN, bool HV, bool HX>
@@ -26,22 +45,23 @@ void launch_masked(const MatView &A, const void *src, const void *X, void *dst, 
     using vec = typename Tr::vec;
     using scal = typename Tr::scal;
     constexpr int U = VN <= 2 ? 8 : 4;
-    const int64_t grid = (A.n + 3) / 4;
-    hipLaunchKernelGGL((clenshaw_step_masked_kernel<Tr, VN, HV, HX, U>), dim3((unsigned)grid),
+    const Grid g = xcd_grid(A.n, 4);
+    hipLaunchKernelGGL((clenshaw_step_masked_kernel<Tr, VN, HV, HX, U>), dim3((unsigned)g.grid),
                        dim3(256), 0, s, (int)A.n, A.rp, A.ci, (const typename Tr::val *)A.val,
                        (const vec *)src, (const vec *)X, (vec *)dst, ldv, p16, (scal)sigma,
-                       (scal)tau, (scal)alpha);
+                       (scal)tau, (scal)alpha, g.group, g.nblocks);
 }
 
 template <class Tr, bool HV, bool HX>
 void dispatch_flags(const MatView &A, const void *src, const void *X, void *dst, int p16,
                     int64_t ldv, double sg, double ta, double al, hipStream_t s) {
+    // exact fits, preferred order: 3-5 vectors per lane, then 2 rows per wave
 #define AFSI_EXACT(VN_, L_)                                                                         \
     if (p16 == (VN_) * (L_)) return launch_exact<Tr, VN_, L_, HV, HX>(A, src, X, dst, ldv, sg, ta, al, s)
-    AFSI_EXACT(1, 64); AFSI_EXACT(2, 64); AFSI_EXACT(3, 64); AFSI_EXACT(4, 64);
-    AFSI_EXACT(5, 64); AFSI_EXACT(6, 64); AFSI_EXACT(8, 64);
-    AFSI_EXACT(1, 32); AFSI_EXACT(3, 32); AFSI_EXACT(5, 32);
-    AFSI_EXACT(1, 16); AFSI_EXACT(3, 16);
+    AFSI_EXACT(4, 32); AFSI_EXACT(4, 64); AFSI_EXACT(3, 64); AFSI_EXACT(5, 64);
+    AFSI_EXACT(3, 32); AFSI_EXACT(5, 32); AFSI_EXACT(2, 64); AFSI_EXACT(2, 32);
+    AFSI_EXACT(6, 64); AFSI_EXACT(8, 64); AFSI_EXACT(1, 64); AFSI_EXACT(1, 32);
+    AFSI_EXACT(3, 16); AFSI_EXACT(1, 16);
 #undef AFSI_EXACT
     if (p16 <= 64) return launch_masked<Tr, 1, HV, HX>(A, src, X, dst, ldv, p16, sg, ta, al, s);
     if (p16 <= 128) return launch_masked<Tr, 2, HV, HX>(A, src, X, dst, ldv, p16, sg, ta, al, s);
@@ -65,15 +85,15 @@ template <class Tr>
 void dispatch_batched(const MatView &A, const void *X, void *P0, void *P1, int p16, int64_t ldv,
                       const BatchArgs &args, hipStream_t s) {
     using vec = typename Tr::vec;
-    const int64_t grid = (A.n + 3) / 4;
+    const Grid g = xcd_grid(A.n, 4);
     if (p16 <= 128) {
-        hipLaunchKernelGGL((clenshaw_batched_kernel<Tr, 2, 4>), dim3((unsigned)grid), dim3(256), 0, s,
-                           (int)A.n, A.rp, A.ci, (const typename Tr::val *)A.val, (const vec *)X,
-                           (vec *)P0, (vec *)P1, ldv, p16, args);
+        hipLaunchKernelGGL((clenshaw_batched_kernel<Tr, 2, 8>), dim3((unsigned)g.grid), dim3(256), 0,
+                           s, (int)A.n, A.rp, A.ci, (const typename Tr::val *)A.val, (const vec *)X,
+                           (vec *)P0, (vec *)P1, ldv, p16, g.group, g.nblocks, args);
     } else {
-        hipLaunchKernelGGL((clenshaw_batched_kernel<Tr, 4, 4>), dim3((unsigned)grid), dim3(256), 0, s,
-                           (int)A.n, A.rp, A.ci, (const typename Tr::val *)A.val, (const vec *)X,
-                           (vec *)P0, (vec *)P1, ldv, p16, args);
+        hipLaunchKernelGGL((clenshaw_batched_kernel<Tr, 4, 8>), dim3((unsigned)g.grid), dim3(256), 0,
+                           s, (int)A.n, A.rp, A.ci, (const typename Tr::val *)A.val, (const vec *)X,
+                           (vec *)P0, (vec *)P1, ldv, p16, g.group, g.nblocks, args);
     }
 }
 
@@ -82,16 +102,16 @@ void dispatch_scalar(const MatView &A, const void *src, const void *X, void *dst
                      int64_t ld, bool hv, bool hx, double sg, double ta, double al, hipStream_t s) {
     using vec = typename Sr::vec;
     using scal = typename Sr::scal;
-    const int64_t grid = (A.n + 3) / 4;
-    hipLaunchKernelGGL((clenshaw_step_scalar_kernel<Sr, 4, 4>), dim3((unsigned)grid), dim3(256), 0, s,
-                       (int)A.n, A.rp, A.ci, (const typename Sr::val *)A.val, (const vec *)src,
+    const Grid g = xcd_grid(A.n, 4);
+    hipLaunchKernelGGL((clenshaw_step_scalar_kernel<Sr, 4, 4>), dim3((unsigned)g.grid), dim3(256), 0,
+                       s, (int)A.n, A.rp, A.ci, (const typename Sr::val *)A.val, (const vec *)src,
                        (const vec *)X, (vec *)dst, ld, p, (int)hv, (int)hx, (scal)sg, (scal)ta,
-                       (scal)al);
+                       (scal)al, g.group, g.nblocks);
 }
 
 }  // namespace afsi
 
-#define AFSI_DEFINE_STEP_ENTRY(NAME, TR, SR)                                                            \
+#define AFSI_DEFINE_STEP_ENTRY(NAME, TR, SR)                                                        \
     namespace afsi {                                                                                \
     void NAME##_step(const MatView &A, const void *src, const void *X, void *dst, int p16,          \
                      int64_t ldv, bool hv, bool hx, double sg, double ta, double al,               \

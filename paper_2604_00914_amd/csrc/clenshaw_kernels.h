@@ -15,11 +15,30 @@
 // index and predicating the multiply-add, never by reading past the row.
 // MASKED variants use L = 64 and loop over chunks of 64*VN vectors with a bounds
 // test, for any width.
+//
+// Memory behaviour (the kernel is HBM-bound):
+//  * src rows are gathered through the caches (each is reused by every row that
+//    references it); dst, the in-place b_{j+2} and X are streamed with
+//    non-temporal accesses so that they do not evict those rows.
+//  * Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+//    L2.  xcd_block() renumbers them so that every XCD works on a contiguous run
+//    of `group` workgroups (a few thousand rows) while all XCDs advance through
+//    the matrix together: neighbouring rows share an L2, and the far neighbours of
+//    a banded matrix are still in the shared memory-side cache when reused.
 #pragma once
 
 #include "vec_types.h"
 
 namespace afsi {
+
+// Logical workgroup index for hardware index b, or -1 for padding workgroups.
+// The grid is a multiple of 8 * group; hardware workgroup b runs on XCD b % 8.
+__device__ inline int xcd_block(int b, int group, int nblocks) {
+    if (group <= 1) return b < nblocks ? b : -1;
+    const int x = b & 7, slot = b >> 3;
+    const int lb = ((slot / group) * 8 + x) * group + slot % group;
+    return lb < nblocks ? lb : -1;
+}
 
 template <class Tr, int VN, int U>
 __device__ inline void gather_accumulate(int start, int end, const int *__restrict__ ci,
@@ -64,12 +83,15 @@ __global__ __launch_bounds__(256) void clenshaw_step_kernel(
     int n, const int *__restrict__ rp, const int *__restrict__ ci,
     const typename Tr::val *__restrict__ va, const typename Tr::vec *__restrict__ src,
     const typename Tr::vec *__restrict__ X, typename Tr::vec *dst, int64_t ldv,
-    typename Tr::scal sigma, typename Tr::scal tau, typename Tr::scal alpha) {
+    typename Tr::scal sigma, typename Tr::scal tau, typename Tr::scal alpha, int group,
+    int nblocks) {
     using vec = typename Tr::vec;
     constexpr int RW = 64 / L;
+    const int lb = xcd_block(blockIdx.x, group, nblocks);
+    if (lb < 0) return;
     const int lane = threadIdx.x & 63;
     const int sub = lane % L;
-    int row = (int)(blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6)) * RW + lane / L;
+    int row = (lb * (int)(blockDim.x / 64) + (int)(threadIdx.x >> 6)) * RW + lane / L;
     if (L == 64) row = __builtin_amdgcn_readfirstlane(row);
     if (row >= n) return;
     const int start = rp[row], end = rp[row + 1];
@@ -82,9 +104,9 @@ __global__ __launch_bounds__(256) void clenshaw_step_kernel(
     for (int v = 0; v < VN; ++v) {
         const int64_t idx = base + v * L;
         vec r = clenshaw_combine<Tr>(sigma, tau, acc[v], src[idx]);
-        if (HAS_V) r = Tr::sub(r, dst[idx]);
-        if (HAS_X) r = Tr::axpy(alpha, X[idx], r);
-        dst[idx] = r;
+        if (HAS_V) r = Tr::sub(r, nt_load(dst + idx));
+        if (HAS_X) r = Tr::axpy(alpha, nt_load(X + idx), r);
+        nt_store(r, dst + idx);
     }
 }
 
@@ -94,16 +116,19 @@ __global__ __launch_bounds__(256) void clenshaw_step_masked_kernel(
     int n, const int *__restrict__ rp, const int *__restrict__ ci,
     const typename Tr::val *__restrict__ va, const typename Tr::vec *__restrict__ src,
     const typename Tr::vec *__restrict__ X, typename Tr::vec *dst, int64_t ldv, int p16,
-    typename Tr::scal sigma, typename Tr::scal tau, typename Tr::scal alpha) {
+    typename Tr::scal sigma, typename Tr::scal tau, typename Tr::scal alpha, int group,
+    int nblocks) {
     using vec = typename Tr::vec;
+    const int lb = xcd_block(blockIdx.x, group, nblocks);
+    if (lb < 0) return;
     const int lane = threadIdx.x & 63;
-    int row = (int)(blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6));
+    int row = lb * (int)(blockDim.x / 64) + (int)(threadIdx.x >> 6);
     row = __builtin_amdgcn_readfirstlane(row);
     if (row >= n) return;
     const int start = rp[row], end = rp[row + 1];
     for (int c0 = 0; c0 < p16; c0 += 64 * VN) {
         // vectors c0 + v*64 + lane that exist in this row
-        const int left = p16 - c0 - lane;  // > 0 for v = 0 if this lane has any
+        const int left = p16 - c0 - lane;
         const int nvalid = left <= 0 ? 0 : (left + 63) / 64;
         vec acc[VN];
 #pragma unroll
@@ -115,9 +140,9 @@ __global__ __launch_bounds__(256) void clenshaw_step_masked_kernel(
             if (v < nvalid) {
                 const int64_t idx = base + v * 64;
                 vec r = clenshaw_combine<Tr>(sigma, tau, acc[v], src[idx]);
-                if (HAS_V) r = Tr::sub(r, dst[idx]);
-                if (HAS_X) r = Tr::axpy(alpha, X[idx], r);
-                dst[idx] = r;
+                if (HAS_V) r = Tr::sub(r, nt_load(dst + idx));
+                if (HAS_X) r = Tr::axpy(alpha, nt_load(X + idx), r);
+                nt_store(r, dst + idx);
             }
         }
     }
@@ -129,10 +154,13 @@ __global__ __launch_bounds__(256) void clenshaw_step_scalar_kernel(
     int n, const int *__restrict__ rp, const int *__restrict__ ci,
     const typename Tr::val *__restrict__ va, const typename Tr::vec *__restrict__ src,
     const typename Tr::vec *__restrict__ X, typename Tr::vec *dst, int64_t ld, int p, int has_v,
-    int has_x, typename Tr::scal sigma, typename Tr::scal tau, typename Tr::scal alpha) {
+    int has_x, typename Tr::scal sigma, typename Tr::scal tau, typename Tr::scal alpha, int group,
+    int nblocks) {
     using vec = typename Tr::vec;
+    const int lb = xcd_block(blockIdx.x, group, nblocks);
+    if (lb < 0) return;
     const int lane = threadIdx.x & 63;
-    int row = (int)(blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6));
+    int row = lb * (int)(blockDim.x / 64) + (int)(threadIdx.x >> 6);
     row = __builtin_amdgcn_readfirstlane(row);
     if (row >= n) return;
     const int start = rp[row], end = rp[row + 1];
@@ -170,11 +198,14 @@ template <class Tr, int VN, int U>
 __global__ __launch_bounds__(256) void clenshaw_batched_kernel(
     int n, const int *__restrict__ rp, const int *__restrict__ ci,
     const typename Tr::val *__restrict__ va, const typename Tr::vec *__restrict__ X,
-    typename Tr::vec *P0, typename Tr::vec *P1, int64_t ldv, int p16, const BatchArgs args) {
+    typename Tr::vec *P0, typename Tr::vec *P1, int64_t ldv, int p16, int group, int nblocks,
+    const BatchArgs args) {
     using vec = typename Tr::vec;
     using scal = typename Tr::scal;
+    const int lb = xcd_block(blockIdx.x, group, nblocks);
+    if (lb < 0) return;
     const int lane = threadIdx.x & 63;
-    int row = (int)(blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6));
+    int row = lb * (int)(blockDim.x / 64) + (int)(threadIdx.x >> 6);
     row = __builtin_amdgcn_readfirstlane(row);
     if (row >= n) return;
     const int start = rp[row], end = rp[row + 1];
@@ -228,9 +259,9 @@ __global__ __launch_bounds__(256) void clenshaw_batched_kernel(
                 vec *dp = args.dst[g] == 1 ? P0 : P1;
                 vec r = clenshaw_combine<Tr>((scal)args.sigma[g], (scal)args.tau[g], acc[v],
                                              sp[v][idx]);
-                if (args.has_v[g]) r = Tr::sub(r, dp[idx]);
-                if (args.alpha[g] != 0.0) r = Tr::axpy((scal)args.alpha[g], X[idx], r);
-                dp[idx] = r;
+                if (args.has_v[g]) r = Tr::sub(r, nt_load(dp + idx));
+                if (args.alpha[g] != 0.0) r = Tr::axpy((scal)args.alpha[g], nt_load(X + idx), r);
+                nt_store(r, dp + idx);
             }
         }
     }

@@ -16,27 +16,6 @@
 
 namespace afsi {
 
-// defined in api.cpp
-void filter_apply(afsi_matrix_t A, const double *coeffs, int degree, int dtype, const void *X,
-                  void *Y, void *work, int64_t p, int64_t ld, hipStream_t s);
-void spmm_apply(afsi_matrix_t A, int dtype, const void *X, void *Y, int64_t p, int64_t ld,
-                hipStream_t s);
-void inner_dev(int dtype, const void *X, int64_t ldx, const void *Y, int64_t ldy, int64_t n,
-               int64_t p, int64_t q, double *G, int64_t ldg, hipStream_t s);
-void gemm_dev(int dtype, const void *X, int64_t ldx, const double *M, int64_t ldm, int64_t n,
-              int64_t p, int64_t q, double alpha, double beta, void *Y, int64_t ldy, hipStream_t s);
-void project_out_dev(int dtype, const void *L, int64_t ldl, int64_t k, void *X, int64_t ldx,
-                     int64_t n, int64_t p, hipStream_t s);
-void orthonormalize_dev(int dtype, void *X, void *W, int64_t n, int64_t p, int64_t ld,
-                        hipStream_t s, double *max_col_norm2);
-void rayleigh_ritz_dev(afsi_matrix_t A, int dtype, const void *Q, void *V, void *AV, int64_t n,
-                       int64_t p, int64_t ld, double *ritz, hipStream_t s);
-void residual_norms_host(int dtype, const void *V, int64_t ldv, const void *AV, int64_t ldav,
-                         const double *lambda, int64_t n, int64_t q, double *out, hipStream_t s);
-void lock_select(const double *ritz, int64_t p, const double *res, uint8_t *I, double a, double b,
-                 double tau_abs, int64_t n_lock, int64_t *n_check_prev, uint8_t *lock, int *done);
-void launch_scale(double *x, int64_t n, int64_t ld, int comp, double s, hipStream_t st);
-
 namespace {
 
 struct DevBuf {

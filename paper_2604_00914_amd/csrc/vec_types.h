@@ -139,6 +139,40 @@ struct SC64 {
     __device__ static inline vec sub(vec a, vec b) { return make_float2(a.x - b.x, a.y - b.y); }
 };
 
+// Streaming (non-temporal) accesses for blocks read or written once per product,
+// so that they do not evict the gathered source rows from L2 and the MALL.
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+typedef float nt_f2 __attribute__((ext_vector_type(2)));
+__device__ inline double nt_load(const double *p) { return __builtin_nontemporal_load(p); }
+__device__ inline float nt_load(const float *p) { return __builtin_nontemporal_load(p); }
+__device__ inline double2 nt_load(const double2 *p) {
+    const nt_d2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_d2 *>(p));
+    return make_double2(v.x, v.y);
+}
+__device__ inline float4 nt_load(const float4 *p) {
+    const nt_f4 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f4 *>(p));
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ inline float2 nt_load(const float2 *p) {
+    const nt_f2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f2 *>(p));
+    return make_float2(v.x, v.y);
+}
+__device__ inline void nt_store(double v, double *p) { __builtin_nontemporal_store(v, p); }
+__device__ inline void nt_store(float v, float *p) { __builtin_nontemporal_store(v, p); }
+__device__ inline void nt_store(double2 v, double2 *p) {
+    const nt_d2 w = {v.x, v.y};
+    __builtin_nontemporal_store(w, reinterpret_cast<nt_d2 *>(p));
+}
+__device__ inline void nt_store(float4 v, float4 *p) {
+    const nt_f4 w = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(w, reinterpret_cast<nt_f4 *>(p));
+}
+__device__ inline void nt_store(float2 v, float2 *p) {
+    const nt_f2 w = {v.x, v.y};
+    __builtin_nontemporal_store(w, reinterpret_cast<nt_f2 *>(p));
+}
+
 // Epilogue shared by every variant:  r = sigma*acc;  r = tau*w + r;  r = r - v;  r = alpha*x + r
 template <class Tr>
 __device__ inline typename Tr::vec clenshaw_combine(typename Tr::scal sigma, typename Tr::scal tau,
