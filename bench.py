@@ -78,6 +78,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=0)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run three plain device copies of one block (counter calibration)")
     args = ap.parse_args()
@@ -226,6 +228,8 @@ def main():
 
     if not args.no_solve:
         out["solve"] = solve_rates(afsi, torch, dev)
+    if not args.no_serve:
+        out["serve"] = serve_rates(afsi, M, args.serve_requests)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, p, k, lmin, lmax, a, b, cfg, sx, args.cpu_sample_steps)
@@ -269,6 +273,62 @@ def solve_rates(afsi, torch, dev):
                 best = rec
         out[form] = best
     M.close()
+    return out
+
+
+def serve_rates(afsi, M_slices, num):
+    """p50/p99 latency and throughput of the continuous-batching server.
+
+    (a) the serving mix: Poisson arrivals, half spectrum slices of the 100^3 matrix
+        (p = 96, degree 120, batched per round), half independent 3D Laplacian +
+        potential matrices (n log-uniform in [1e4, 1e6], p in {32..256}, degree in
+        [40, 200]); a fixed budget of 2 iterations per request bounds the run;
+    (b) a converging stream of 2D Laplacian window requests (40 eigenpairs each),
+        for eigenpairs/s.  Both in FP64 and in the mixed form.
+    """
+    from paper_2604_00914_amd import serve
+    from workloads import build_config, laplacian_3d_dirichlet
+    from workloads.stream import serving_stream
+
+    reqs = serving_stream(num, rate_hz=8.0, seed=0)
+    mats = {}
+    for r in reqs:
+        if r.kind == "matrix" and r.grid not in mats:
+            mats[r.grid] = afsi.Matrix(laplacian_3d_dirichlet(r.grid, 2.0, seed=r.seed), bounds=(0.0, 14.0))
+    out = {"mix": {"requests": num, "rate_hz": 8.0, "max_iter": 2,
+                   "slices": sum(r.kind == "slice" for r in reqs)}}
+    for form in ("fp64", "mixed"):
+        jobs = []
+        for r in reqs:
+            o = afsi.afsi_options_default(r.degree)
+            o.max_iter = 2
+            if form == "mixed":
+                o.filter_dtype, o.tau_c = afsi.R32, 1e-6
+            M = M_slices if r.kind == "slice" else mats[r.grid]
+            jobs.append((r.arrival, M, r.a, r.b, r.p, o, r.seed, r.kind))
+        with serve.Server(hbm_budget_bytes=200 << 30) as S:
+            S.set_pool_columns(M_slices, 16 * 96)
+            rep = serve.run_stream(S, jobs)
+        out["mix"][form] = rep.summary()
+        log(f"serve mix {form}: {out['mix'][form]}")
+    A, (lmin, lmax), (a, b), cfg = build_config("lap2d_64")
+    M1 = afsi.Matrix(A, bounds=(lmin, lmax))
+    rng = np.random.default_rng(1)
+    arrivals = np.cumsum(rng.exponential(1.0 / 40.0, size=16))
+    out["converging"] = {"workload": cfg.name, "requests": 16, "rate_hz": 40.0}
+    for form in ("fp64", "mixed"):
+        o = afsi.afsi_options_default(cfg.degree)
+        if form == "mixed":
+            o.filter_dtype, o.tau_c = afsi.R32, 1e-6
+        jobs = [(float(t), M1, a, b, cfg.p, o, 500 + i, i) for i, t in enumerate(arrivals)]
+        with serve.Server(hbm_budget_bytes=64 << 30) as S:
+            S.set_pool_columns(M1, 16 * cfg.p)
+            rep = serve.run_stream(S, jobs)
+        out["converging"][form] = rep.summary()
+        log(f"serve converging {form}: {out['converging'][form]}")
+    for M in mats.values():
+        M.close()
+    M1.close()
     return out
 
 

@@ -311,6 +311,66 @@ int afsi_solve(afsi_matrix_t A, double a, double b, const afsi_options *opts, af
                afsi_block *evecs, int64_t capacity, double *eigenvalues, double *residuals,
                afsi_result *result, void *stream);
 
+/* ------------------------------------------------------------------ serving */
+
+/*
+ * Continuous-batching server for many solves on one device (spectrum slicing of
+ * one matrix, Section 1, and independent matrices).  Requests are admitted when
+ * their device footprint fits `hbm_budget_bytes`: a pool of three concatenated
+ * n x cols FP64 blocks per (matrix, filter dtype) (three more in FP32 for the
+ * mixed form) plus n x p for the request's eigenvectors.  All filtering requests
+ * of a pool advance together, one batched Clenshaw product (A read once) per
+ * round; each pool runs on its own HIP stream and host thread, so independent
+ * matrices overlap on the device.  A request's results do not depend on what
+ * else is running.  Matrices must outlive the requests that use them.
+ */
+typedef struct afsi_server_s *afsi_server_t;
+
+typedef struct {
+    int32_t state;       /* 0 queued, 1 running, 2 done, 3 failed */
+    int32_t status;      /* afsi_status of a finished request (AFSI_E_NOCONV: iteration limit) */
+    int64_t count;       /* eigenpairs found so far */
+    int32_t iterations;
+    int32_t converged;
+    int64_t spmv;
+    double avg_degree;
+    double t_submit, t_admit, t_done; /* seconds on the server's clock */
+} afsi_request_info;
+
+typedef struct {
+    int64_t bytes_in_use, budget;
+    int64_t queued, running, done, pools;
+    int64_t batched_launches, batched_groups; /* groups / launches = slices per launch */
+    double now;                               /* server clock (s) */
+} afsi_server_stats;
+
+int afsi_server_create(int device, int64_t hbm_budget_bytes, afsi_server_t *out);
+/* Stops the pool threads (running requests fail), frees everything. */
+int afsi_server_destroy(afsi_server_t S);
+/* Reserve `cols` columns for A's pools (slices of one matrix share them). */
+int afsi_server_set_pool_columns(afsi_server_t S, afsi_matrix_t A, int64_t cols);
+/*
+ * Queue a solve of [a, b] on A (bounds set) with block width p and `opts`
+ * (opts->filter_dtype picks the plain or mixed form).  The start block is N(0,1)
+ * from a counter-based generator keyed by `seed`.  AFSI_E_BUSY if the request
+ * cannot fit the budget even alone.  Returns at once.
+ */
+int afsi_server_submit(afsi_server_t S, afsi_matrix_t A, double a, double b, int64_t p,
+                       const afsi_options *opts, uint64_t seed, int64_t *id);
+int afsi_server_info(afsi_server_t S, int64_t id, afsi_request_info *info);
+/* Block until request `id` finishes or `timeout_s` passes (info->state tells which). */
+int afsi_server_wait(afsi_server_t S, int64_t id, double timeout_s, afsi_request_info *info);
+/* Next finished request id in completion order, or -1 after `timeout_s`. */
+int afsi_server_wait_any(afsi_server_t S, double timeout_s, int64_t *id);
+/*
+ * Copy a finished request's eigenvalues / residuals (host, `capacity` entries)
+ * and eigenvectors (device block, n x count or wider; NULL to skip) and release
+ * the request.  Synchronises `stream`.
+ */
+int afsi_server_fetch(afsi_server_t S, int64_t id, double *eigenvalues, double *residuals,
+                      int64_t capacity, afsi_block *evecs, void *stream);
+int afsi_server_get_stats(afsi_server_t S, afsi_server_stats *st);
+
 #ifdef __cplusplus
 }
 #endif

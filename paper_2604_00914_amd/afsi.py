@@ -57,6 +57,19 @@ class afsi_result(C.Structure):
                 ("time_host_ms", C.c_double)]
 
 
+class afsi_request_info(C.Structure):
+    _fields_ = [("state", C.c_int32), ("status", C.c_int32), ("count", C.c_int64),
+                ("iterations", C.c_int32), ("converged", C.c_int32), ("spmv", C.c_int64),
+                ("avg_degree", C.c_double), ("t_submit", C.c_double), ("t_admit", C.c_double),
+                ("t_done", C.c_double)]
+
+
+class afsi_server_stats(C.Structure):
+    _fields_ = [("bytes_in_use", C.c_int64), ("budget", C.c_int64), ("queued", C.c_int64),
+                ("running", C.c_int64), ("done", C.c_int64), ("pools", C.c_int64),
+                ("batched_launches", C.c_int64), ("batched_groups", C.c_int64), ("now", C.c_double)]
+
+
 _P = C.c_void_p
 _I64P = C.POINTER(C.c_int64)
 _DP = C.POINTER(C.c_double)
@@ -90,6 +103,15 @@ _SIGS = {
     "afsi_host_cholesky_inverse": (C.c_int, [C.c_int64, C.c_int32, _P, C.c_int64, C.c_double]),
     "afsi_options_default": (None, [C.POINTER(afsi_options), C.c_int]),
     "afsi_solve": (C.c_int, [_P, C.c_double, C.c_double, C.POINTER(afsi_options), _BP, _BP, C.c_int64, _P, _P, C.POINTER(afsi_result), _P]),
+    "afsi_server_create": (C.c_int, [C.c_int, C.c_int64, C.POINTER(_P)]),
+    "afsi_server_destroy": (C.c_int, [_P]),
+    "afsi_server_set_pool_columns": (C.c_int, [_P, _P, C.c_int64]),
+    "afsi_server_submit": (C.c_int, [_P, _P, C.c_double, C.c_double, C.c_int64, C.POINTER(afsi_options), C.c_uint64, _I64P]),
+    "afsi_server_info": (C.c_int, [_P, C.c_int64, C.POINTER(afsi_request_info)]),
+    "afsi_server_wait": (C.c_int, [_P, C.c_int64, C.c_double, C.POINTER(afsi_request_info)]),
+    "afsi_server_wait_any": (C.c_int, [_P, C.c_double, _I64P]),
+    "afsi_server_fetch": (C.c_int, [_P, C.c_int64, _P, _P, C.c_int64, _BP, _P]),
+    "afsi_server_get_stats": (C.c_int, [_P, C.POINTER(afsi_server_stats)]),
 }
 
 _lib = None
@@ -101,6 +123,13 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise AfsiError(-8, f"{LIB_PATH} is not built; run paper_2604_00914_amd.build.build()")
+        # torch ships its own HIP runtime (same soname as ROCm's).  Loading torch first
+        # makes libafsi.so bind to that already-loaded runtime, so one process never
+        # holds two HIP runtimes (which leaves the second without devices).
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             f = getattr(L, name)
@@ -337,6 +366,61 @@ def afsi_solve(h, a: float, b: float, opts: afsi_options, X0, evecs, capacity: i
     if st not in (0, -6):
         _check(st)
     return st, lam[: r.count].copy(), res[: r.count].copy(), r
+
+
+def afsi_server_create(device: int, hbm_budget_bytes: int):
+    h = C.c_void_p()
+    _check(lib().afsi_server_create(device, int(hbm_budget_bytes), C.byref(h)))
+    return h
+
+
+def afsi_server_destroy(S):
+    _check(lib().afsi_server_destroy(S))
+
+
+def afsi_server_set_pool_columns(S, A, cols: int):
+    _check(lib().afsi_server_set_pool_columns(S, A, cols))
+
+
+def afsi_server_submit(S, A, a: float, b: float, p: int, opts: afsi_options, seed: int) -> int:
+    rid = C.c_int64()
+    _check(lib().afsi_server_submit(S, A, a, b, p, C.byref(opts), seed, C.byref(rid)))
+    return rid.value
+
+
+def afsi_server_info(S, rid: int) -> afsi_request_info:
+    info = afsi_request_info()
+    _check(lib().afsi_server_info(S, rid, C.byref(info)))
+    return info
+
+
+def afsi_server_wait(S, rid: int, timeout_s: float) -> afsi_request_info:
+    info = afsi_request_info()
+    _check(lib().afsi_server_wait(S, rid, timeout_s, C.byref(info)))
+    return info
+
+
+def afsi_server_wait_any(S, timeout_s: float) -> int:
+    rid = C.c_int64()
+    _check(lib().afsi_server_wait_any(S, timeout_s, C.byref(rid)))
+    return rid.value
+
+
+def afsi_server_fetch(S, rid: int, capacity: int, evecs=None, stream=None):
+    """Returns (eigenvalues, residuals) and copies eigenvectors into `evecs` if given."""
+    lam = np.zeros(max(capacity, 1))
+    res = np.zeros(max(capacity, 1))
+    info = afsi_server_info(S, rid)
+    _check(lib().afsi_server_fetch(S, rid, _ptr(lam), _ptr(res), capacity,
+                                   _bref(_blk(evecs)) if evecs is not None else None,
+                                   _stream(stream) if evecs is not None else None))
+    return lam[: info.count].copy(), res[: info.count].copy()
+
+
+def afsi_server_get_stats(S) -> afsi_server_stats:
+    st = afsi_server_stats()
+    _check(lib().afsi_server_get_stats(S, C.byref(st)))
+    return st
 
 
 def _blk(x):

@@ -577,12 +577,24 @@ int afsi_clenshaw_step_batched(afsi_matrix_t A, int ngroups, const afsi_step_gro
         AFSI_REQUIRE(X->rows == A->n, "X rows != n");
         AFSI_REQUIRE(!overlap(X, P0) && !overlap(X, P1) && !overlap(P0, P1),
                      "X, P0 and P1 must not overlap");
+        DeviceGuard dg(A->device);
+        batched_step(A, ngroups, groups, X->dtype, X->ptr, P0->ptr, P1->ptr, X->cols, X->ld,
+                     as_stream(stream));
+    });
+}
+
+}  // extern "C"
+
+namespace afsi {
+
+void batched_step(afsi_matrix_t A, int ngroups, const afsi_step_group *groups, int dtype,
+                  const void *Xp, void *P0p, void *P1p, int64_t ptot, int64_t ld, hipStream_t s) {
+    {
         AFSI_REQUIRE(ngroups >= 0 && ngroups <= 64, "ngroups must be in 0..64");
         AFSI_REQUIRE(ngroups == 0 || groups, "groups is NULL");
-        const int eb = elem_bytes(X->dtype);
+        const int eb = elem_bytes(dtype);
         const int E = 16 / eb;
-        AFSI_REQUIRE((X->ld * eb) % 16 == 0 && aligned16(X->ptr) && aligned16(P0->ptr) &&
-                         aligned16(P1->ptr),
+        AFSI_REQUIRE((ld * eb) % 16 == 0 && aligned16(Xp) && aligned16(P0p) && aligned16(P1p),
                      "batched step needs 16-byte aligned rows");
         BatchArgs args;
         std::memset(&args, 0, sizeof args);
@@ -590,7 +602,7 @@ int afsi_clenshaw_step_batched(afsi_matrix_t A, int ngroups, const afsi_step_gro
         for (int g = 0; g < ngroups; ++g) {
             const afsi_step_group &G = groups[g];
             if (!G.active || G.ncols == 0) continue;
-            AFSI_REQUIRE(G.col0 >= 0 && G.ncols > 0 && G.col0 + G.ncols <= X->cols,
+            AFSI_REQUIRE(G.col0 >= 0 && G.ncols > 0 && G.col0 + G.ncols <= ptot,
                          "group %d columns out of range", g);
             AFSI_REQUIRE(G.col0 % E == 0 && G.ncols % E == 0,
                          "group %d: col0 and ncols must be multiples of %d", g, E);
@@ -611,20 +623,36 @@ int afsi_clenshaw_step_batched(afsi_matrix_t A, int ngroups, const afsi_step_gro
             args.alpha[k] = G.alpha;
         }
         if (args.ngroups == 0 || A->n == 0) return;
-        DeviceGuard dg(A->device);
-        hipStream_t s = as_stream(stream);
-        const MatView mv = matrix_view(A, X->dtype, s);
-        const int p16 = (int)((X->cols * eb + 15) / 16);
-        const int64_t ldv = X->ld * eb / 16;
-        switch (X->dtype) {
-        case AFSI_R64: clenshaw_r64_batched(mv, X->ptr, P0->ptr, P1->ptr, p16, ldv, args, s); break;
-        case AFSI_R32: clenshaw_r32_batched(mv, X->ptr, P0->ptr, P1->ptr, p16, ldv, args, s); break;
-        case AFSI_C128: clenshaw_c128_batched(mv, X->ptr, P0->ptr, P1->ptr, p16, ldv, args, s); break;
-        case AFSI_C64: clenshaw_c64_batched(mv, X->ptr, P0->ptr, P1->ptr, p16, ldv, args, s); break;
+        const MatView mv = matrix_view(A, dtype, s);
+        const int p16 = (int)((ptot * eb + 15) / 16);
+        const int64_t ldv = ld * eb / 16;
+        switch (dtype) {
+        case AFSI_R64: clenshaw_r64_batched(mv, Xp, P0p, P1p, p16, ldv, args, s); break;
+        case AFSI_R32: clenshaw_r32_batched(mv, Xp, P0p, P1p, p16, ldv, args, s); break;
+        case AFSI_C128: clenshaw_c128_batched(mv, Xp, P0p, P1p, p16, ldv, args, s); break;
+        case AFSI_C64: clenshaw_c64_batched(mv, Xp, P0p, P1p, p16, ldv, args, s); break;
         }
         AFSI_HIP(hipGetLastError());
-    });
+    }
 }
+
+void gather_cols(int dtype, const void *src, int64_t n, int64_t ld, const int32_t *cols,
+                 int64_t count, void *dst, int64_t ldd, hipStream_t s) {
+    if (count == 0 || n == 0) return;
+    afsi_block sb{const_cast<void *>(src), n, ld, ld, dtype};
+    afsi_block db{dst, n, count, ldd, dtype};
+    Workspace &ws = workspace(s);
+    int32_t *d = (int32_t *)ws.dev_reserve(SLOT_GATHER, sizeof(int32_t) * count);
+    int32_t *h = (int32_t *)ws.host_reserve(1, sizeof(int32_t) * count);
+    std::memcpy(h, cols, sizeof(int32_t) * count);
+    AFSI_HIP(hipMemcpyAsync(d, h, sizeof(int32_t) * count, hipMemcpyHostToDevice, s));
+    launch_gather_columns(sb, d, count, db, s);
+    AFSI_HIP(hipStreamSynchronize(s));  // the index list lives in reusable scratch
+}
+
+}  // namespace afsi
+
+extern "C" {
 
 int afsi_block_inner(const afsi_block *X, const afsi_block *Y, afsi_block *G, void *stream) {
     return guarded([&] {

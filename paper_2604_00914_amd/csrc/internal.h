@@ -196,6 +196,13 @@ void residual_norms_host(int dtype, const void *V, int64_t ldv, const void *AV, 
 void lock_select(const double *ritz, int64_t p, const double *res, uint8_t *I, double a, double b,
                  double tau_abs, int64_t n_lock, int64_t *n_check_prev, uint8_t *lock, int *done);
 void launch_scale(double *x, int64_t n, int64_t ld, int comp, double s, hipStream_t st);
+void launch_fill_normal(double *x, int64_t n, int64_t p, int64_t ld, int comp, uint64_t seed,
+                        hipStream_t st);
+// Gather columns of src (n rows, ld) into dst columns [0, count) (ld ldd); synchronises s.
+void gather_cols(int dtype, const void *src, int64_t n, int64_t ld, const int32_t *cols,
+                 int64_t count, void *dst, int64_t ldd, hipStream_t s);
+void batched_step(afsi_matrix_t A, int ngroups, const afsi_step_group *groups, int dtype,
+                  const void *X, void *P0, void *P1, int64_t ptot, int64_t ld, hipStream_t s);
 
 // ---------------------------------------------------------------- host linear algebra
 

@@ -1,0 +1,664 @@
+// Continuous-batching request server for interior eigen-solves on one GPU.
+//
+// Requests (matrix, interval, block width, options, seed) are admitted when their
+// device footprint fits a byte budget.  Admitted requests of the same matrix and
+// filter precision share a pool: three concatenated FP64 blocks (plus three in the
+// filter precision for the mixed form) whose column ranges are handed out to
+// requests, so the CSR matrix and every request's subspace stay resident.  Each
+// pool has its own HIP stream and host thread.  A pool thread repeats rounds:
+//   * one batched Clenshaw product (afsi_clenshaw_step_batched semantics) for every
+//     request that is filtering, whatever product index each one is at - the
+//     matrix is read once for all of them;
+//   * the dense phases (Cholesky QR, Rayleigh-Ritz, residuals, locking - the steps
+//     of Algorithm 4) of every request whose filter just finished.
+// Requests that arrive while others run are admitted as soon as columns and bytes
+// free up; independent matrices progress concurrently on their own streams.  A
+// request's column arithmetic does not depend on its neighbours, so its results
+// are bit-identical alone and in a mix.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <list>
+#include <map>
+#include <memory>
+#include <numeric>
+#include <thread>
+#include <vector>
+
+#include "internal.h"
+
+namespace afsi {
+namespace srv {
+
+enum { Q_QUEUED = 0, Q_RUNNING = 1, Q_DONE = 2, Q_FAILED = 3 };
+enum { PH_INIT = 0, PH_FILTER = 1, PH_DENSE = 2 };
+
+struct Pool;
+
+struct Request {
+    int64_t id = 0;
+    afsi_matrix_t A = nullptr;
+    double a = 0, b = 0;
+    int64_t p = 0;
+    afsi_options opts{};
+    uint64_t seed = 0;
+    int dt = AFSI_R64, fdt = AFSI_R64;
+    int state = Q_QUEUED, status = AFSI_OK;
+    std::string error;
+    double t_submit = 0, t_admit = 0, t_done = 0;
+    std::vector<double> lam, res;
+    void *evecs = nullptr;  // n x p, ld = p, FP64 domain dtype
+    int64_t n_lock = 0;
+    int iterations = 0, converged = 0;
+    int64_t spmv = 0;
+    double avg_degree = 0;
+    size_t evec_bytes = 0;
+};
+
+struct Session {
+    Request *r = nullptr;
+    int64_t col0 = 0, cap = 0, p_act = 0;
+    std::vector<double> coeffs;
+    double l1 = 0, l2 = 0, tau_abs = 0;
+    int k_cur = 1, step = 0, phase = PH_INIT;
+    int64_t n_check_prev = 0;
+    std::vector<int> degrees;
+};
+
+struct Server;
+
+struct Pool {
+    Server *S = nullptr;
+    afsi_matrix_t A = nullptr;
+    int dt = AFSI_R64, fdt = AFSI_R64;
+    int64_t n = 0, cap = 0, E = 1;
+    void *B[3] = {nullptr, nullptr, nullptr};  // FP64: active block, filter output / Q, work / AV
+    void *F[3] = {nullptr, nullptr, nullptr};  // filter precision (mixed form only)
+    hipStream_t stream = nullptr;
+    std::vector<uint8_t> used;  // per column
+    std::list<Session> sessions;
+    std::deque<Session> incoming;
+    size_t bytes = 0;
+    bool mixed() const { return fdt != dt; }
+};
+
+struct Server {
+    int device = 0;
+    int64_t budget = 0, in_use = 0;
+    std::mutex mu;
+    std::condition_variable cv;     // request completions / thread exits
+    std::deque<Request *> queue;
+    std::map<int64_t, std::unique_ptr<Request>> reqs;
+    std::map<std::pair<afsi_matrix_t, int>, Pool *> pools;
+    std::map<afsi_matrix_t, int64_t> pool_cols;
+    std::deque<int64_t> finished;
+    int64_t next_id = 1, n_done = 0;
+    int live_threads = 0;
+    bool stopping = false;
+    int64_t launches = 0, launch_groups = 0;
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+    double now() const {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+};
+
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+int64_t col_align(int dt, int fdt) {
+    return std::max<int64_t>(16 / elem_bytes(dt), 16 / elem_bytes(fdt));
+}
+
+size_t pool_bytes(int64_t n, int64_t cap, int dt, int fdt) {
+    size_t b = 3 * (size_t)n * cap * elem_bytes(dt);
+    if (fdt != dt) b += 3 * (size_t)n * cap * elem_bytes(fdt);
+    return b;
+}
+
+int64_t find_run(const std::vector<uint8_t> &used, int64_t need, int64_t E) {
+    const int64_t cap = (int64_t)used.size();
+    for (int64_t c = 0; c + need <= cap; c += E) {
+        bool ok = true;
+        for (int64_t j = c; j < c + need; ++j)
+            if (used[j]) {
+                ok = false;
+                break;
+            }
+        if (ok) return c;
+    }
+    return -1;
+}
+
+void pool_thread(Pool *P);
+
+// Admit every queued request that fits (caller holds S->mu).
+void try_admit(Server *S) {
+    for (auto it = S->queue.begin(); it != S->queue.end();) {
+        Request *r = *it;
+        const auto key = std::make_pair(r->A, r->fdt);
+        const int64_t E = col_align(r->dt, r->fdt);
+        const int64_t need = round_up(r->p, E);
+        Pool *P = nullptr;
+        auto pit = S->pools.find(key);
+        int64_t col0 = -1;
+        size_t new_pool = 0;
+        if (pit != S->pools.end()) {
+            P = pit->second;
+            col0 = find_run(P->used, need, E);
+            if (col0 < 0) {
+                ++it;
+                continue;
+            }
+        } else {
+            int64_t cap = need;
+            auto h = S->pool_cols.find(r->A);
+            if (h != S->pool_cols.end()) cap = std::max(cap, round_up(h->second, E));
+            new_pool = pool_bytes(r->A->n, cap, r->dt, r->fdt);
+            if (S->in_use + (int64_t)(new_pool + r->evec_bytes) > S->budget) {
+                ++it;
+                continue;
+            }
+            std::unique_ptr<Pool> np(new Pool());
+            np->S = S;
+            np->A = r->A;
+            np->dt = r->dt;
+            np->fdt = r->fdt;
+            np->n = r->A->n;
+            np->cap = cap;
+            np->E = E;
+            np->used.assign(cap, 0);
+            try {
+                DeviceGuard dg(S->device);
+                const size_t blk = (size_t)np->n * cap * elem_bytes(r->dt);
+                for (auto &b : np->B) AFSI_HIP(hipMalloc(&b, std::max<size_t>(blk, 16)));
+                if (np->mixed()) {
+                    const size_t fb = (size_t)np->n * cap * elem_bytes(r->fdt);
+                    for (auto &b : np->F) AFSI_HIP(hipMalloc(&b, std::max<size_t>(fb, 16)));
+                }
+                AFSI_HIP(hipStreamCreateWithFlags(&np->stream, hipStreamNonBlocking));
+            } catch (...) {
+                for (auto b : np->B) (void)hipFree(b);
+                for (auto b : np->F) (void)hipFree(b);
+                ++it;
+                continue;
+            }
+            np->bytes = new_pool;
+            S->in_use += (int64_t)new_pool;
+            P = np.release();
+            S->pools[key] = P;
+            ++S->live_threads;
+            std::thread(pool_thread, P).detach();
+            col0 = 0;
+        }
+        if (S->in_use + (int64_t)r->evec_bytes > S->budget) {
+            ++it;
+            continue;
+        }
+        try {
+            DeviceGuard dg(S->device);
+            AFSI_HIP(hipMalloc(&r->evecs, std::max<size_t>(r->evec_bytes, 16)));
+        } catch (...) {
+            ++it;
+            continue;
+        }
+        S->in_use += (int64_t)r->evec_bytes;
+        for (int64_t j = col0; j < col0 + need; ++j) P->used[j] = 1;
+        Session s;
+        s.r = r;
+        s.col0 = col0;
+        s.cap = need;
+        s.p_act = r->p;
+        r->state = Q_RUNNING;
+        r->t_admit = S->now();
+        P->incoming.push_back(std::move(s));
+        it = S->queue.erase(it);
+    }
+    S->cv.notify_all();
+}
+
+void *col_ptr(void *base, int64_t col, int dt) {
+    return (char *)base + (size_t)col * elem_bytes(dt);
+}
+
+void finish(Pool *P, Session &s, int status, const std::string &err) {
+    Server *S = P->S;
+    Request *r = s.r;
+    std::lock_guard<std::mutex> lk(S->mu);
+    r->status = status;
+    r->error = err;
+    r->state = (status == AFSI_OK || status == AFSI_E_NOCONV) ? Q_DONE : Q_FAILED;
+    r->converged = status == AFSI_OK;
+    r->avg_degree = s.degrees.empty()
+                        ? 0.0
+                        : std::accumulate(s.degrees.begin(), s.degrees.end(), 0.0) / s.degrees.size();
+    r->t_done = S->now();
+    for (int64_t j = s.col0; j < s.col0 + s.cap; ++j) P->used[j] = 0;
+    S->finished.push_back(r->id);
+    ++S->n_done;
+    S->cv.notify_all();
+}
+
+// Start block from the request's seed, orthonormalised (Algorithm 4, initialisation).
+void init_session(Pool *P, Session &s) {
+    Request *r = s.r;
+    const int comp = is_complex(P->dt) ? 2 : 1;
+    void *B0 = col_ptr(P->B[0], s.col0, P->dt);
+    launch_fill_normal((double *)B0, P->n, r->p, P->cap, comp, r->seed, P->stream);
+    orthonormalize_dev(P->dt, B0, col_ptr(P->B[1], s.col0, P->dt), P->n, r->p, P->cap, P->stream,
+                       nullptr);
+    s.coeffs.resize(r->opts.kmax + 1);
+    filter_coefficients(r->A->lmin, r->A->lmax, r->a, r->b, r->opts.kmax, r->opts.damping,
+                        r->opts.m_exp, s.coeffs.data());
+    const double w = r->A->lmax - r->A->lmin;
+    s.l1 = 2.0 / w;
+    s.l2 = -(r->A->lmax + r->A->lmin) / w;
+    s.tau_abs = r->opts.tau_c * std::max(std::fabs(r->A->lmin), std::fabs(r->A->lmax));
+    s.k_cur = r->opts.kmax;
+    if (r->opts.k_init > 0) {
+        s.k_cur = std::min(r->opts.k_init, r->opts.kmax);
+    } else if (r->opts.adaptive) {
+        const double ta = std::min(1.0, std::max(-1.0, (2 * r->a - r->A->lmax - r->A->lmin) / w));
+        const double tb = std::min(1.0, std::max(-1.0, (2 * r->b - r->A->lmax - r->A->lmin) / w));
+        s.k_cur = std::max(1, std::min((int)std::ceil(r->opts.C / (std::acos(ta) - std::acos(tb))) - 1,
+                                       r->opts.kmax));
+    }
+}
+
+void start_filter(Pool *P, Session &s) {
+    s.phase = PH_FILTER;
+    s.step = 0;
+    if (P->mixed()) {
+        afsi_block src{col_ptr(P->B[0], s.col0, P->dt), P->n, s.p_act, P->cap, P->dt};
+        afsi_block dst{col_ptr(P->F[0], s.col0, P->fdt), P->n, s.p_act, P->cap, P->fdt};
+        launch_convert(src, dst, P->stream);
+    }
+}
+
+enum { DP_CONTINUE = 0, DP_CONVERGED = 1, DP_LIMIT = 2 };
+
+// One pass of the dense steps after a filter; says whether the request goes on.
+int dense_phase(Pool *P, Session &s) {
+    Request *r = s.r;
+    const int dt = P->dt;
+    const int64_t n = P->n, ld = P->cap, pa = s.p_act;
+    const int outi = 1 + (s.k_cur - 1) % 2;  // product output lands in P[(k-1) % 2]
+    void *q, *w;
+    if (P->mixed()) {
+        afsi_block src{col_ptr(P->F[outi], s.col0, P->fdt), n, pa, ld, P->fdt};
+        afsi_block dst{col_ptr(P->B[1], s.col0, dt), n, pa, ld, dt};
+        launch_convert(src, dst, P->stream);
+        q = col_ptr(P->B[1], s.col0, dt);
+        w = col_ptr(P->B[2], s.col0, dt);
+    } else {
+        q = col_ptr(P->B[outi], s.col0, dt);
+        w = col_ptr(P->B[3 - outi], s.col0, dt);
+    }
+    void *v = col_ptr(P->B[0], s.col0, dt);
+    r->spmv += (int64_t)s.k_cur * pa;
+    s.degrees.push_back(s.k_cur);
+    ++r->iterations;
+    if (r->n_lock > 0) project_out_dev(dt, r->evecs, r->p, r->n_lock, q, ld, n, pa, P->stream);
+    double maxn2 = 0.0;
+    orthonormalize_dev(dt, q, w, n, pa, ld, P->stream, &maxn2);
+    if (r->opts.damping != AFSI_DAMP_NONE && maxn2 > 16.0)
+        AFSI_FAIL(AFSI_E_BOUNDS, "filtered block grew by %.3g: spectral bounds do not enclose A",
+                  std::sqrt(maxn2));
+    std::vector<double> ritz(pa), res(pa);
+    rayleigh_ritz_dev(r->A, dt, q, v, w, n, pa, ld, ritz.data(), P->stream);
+    r->spmv += pa;
+    std::vector<uint8_t> I(pa), lock(pa);
+    int64_t e = 0;
+    for (int64_t j = 0; j < pa; ++j) {
+        I[j] = ritz[j] >= r->a && ritz[j] <= r->b;
+        e += I[j];
+    }
+    if (e > 0) {
+        if (r->opts.adaptive)
+            s.k_cur = select_degree(ritz.data(), pa, e, s.coeffs.data(), r->opts.kmax, s.l1, s.l2,
+                                    r->opts.tau_a);
+        residual_norms_host(dt, v, ld, w, ld, ritz.data(), n, pa, res.data(), P->stream);
+        int done = 0;
+        lock_select(ritz.data(), pa, res.data(), I.data(), r->a, r->b, s.tau_abs, r->n_lock,
+                    &s.n_check_prev, lock.data(), &done);
+        std::vector<int32_t> lk, keep;
+        for (int64_t j = 0; j < pa; ++j) (lock[j] ? lk : keep).push_back((int32_t)j);
+        if (!lk.empty()) {
+            AFSI_REQUIRE(r->n_lock + (int64_t)lk.size() <= r->p, "locked more pairs than columns");
+            for (auto j : lk) {
+                r->lam.push_back(ritz[j]);
+                r->res.push_back(res[j]);
+            }
+            gather_cols(dt, v, n, ld, lk.data(), (int64_t)lk.size(), col_ptr(r->evecs, r->n_lock, dt),
+                        r->p, P->stream);
+            if (!keep.empty()) {
+                gather_cols(dt, v, n, ld, keep.data(), (int64_t)keep.size(), w, ld, P->stream);
+                const int eb = elem_bytes(dt);
+                AFSI_HIP(hipMemcpy2DAsync(v, ld * eb, w, ld * eb, keep.size() * eb, n,
+                                          hipMemcpyDeviceToDevice, P->stream));
+            }
+            r->n_lock += (int64_t)lk.size();
+            s.p_act -= (int64_t)lk.size();
+        }
+        if (done) return DP_CONVERGED;
+    }
+    if (r->iterations >= r->opts.max_iter) return DP_LIMIT;
+    start_filter(P, s);
+    return DP_CONTINUE;
+}
+
+void sort_results(Pool *P, Request *r) {
+    if (r->n_lock < 2) return;
+    std::vector<int32_t> order(r->n_lock);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return r->lam[x] < r->lam[y]; });
+    std::vector<double> lam(r->n_lock), res(r->n_lock);
+    for (int64_t t = 0; t < r->n_lock; ++t) lam[t] = r->lam[order[t]], res[t] = r->res[order[t]];
+    r->lam = lam;
+    r->res = res;
+    // permute the eigenvector columns through the pool's work block
+    const int dt = P->dt, eb = elem_bytes(dt);
+    void *tmp = nullptr;
+    AFSI_HIP(hipMalloc(&tmp, (size_t)P->n * r->n_lock * eb));
+    gather_cols(dt, r->evecs, P->n, r->p, order.data(), r->n_lock, tmp, r->n_lock, P->stream);
+    AFSI_HIP(hipMemcpy2DAsync(r->evecs, r->p * eb, tmp, r->n_lock * eb, r->n_lock * eb, P->n,
+                              hipMemcpyDeviceToDevice, P->stream));
+    AFSI_HIP(hipStreamSynchronize(P->stream));
+    (void)hipFree(tmp);
+}
+
+void release_pool(Pool *P) {
+    // caller holds S->mu; the pool has no sessions
+    Server *S = P->S;
+    S->pools.erase(std::make_pair(P->A, P->fdt));
+    S->in_use -= (int64_t)P->bytes;
+    (void)hipStreamSynchronize(P->stream);
+    for (auto b : P->B) (void)hipFree(b);
+    for (auto b : P->F) (void)hipFree(b);
+    (void)hipStreamDestroy(P->stream);
+}
+
+void pool_thread(Pool *P) {
+    Server *S = P->S;
+    (void)hipSetDevice(S->device);
+    std::vector<afsi_step_group> groups;
+    std::vector<Session *> filt;
+    for (;;) {
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            while (!P->incoming.empty()) {
+                P->sessions.push_back(std::move(P->incoming.front()));
+                P->incoming.pop_front();
+            }
+            if (P->sessions.empty() || S->stopping) {
+                for (auto &s : P->sessions) {
+                    s.r->state = Q_FAILED;
+                    s.r->status = AFSI_E_INVALID;
+                    s.r->error = "server stopped";
+                }
+                release_pool(P);
+                --S->live_threads;
+                try_admit(S);
+                S->cv.notify_all();
+                delete P;
+                return;
+            }
+        }
+        // sessions that need initialisation, one batched product, then dense phases
+        std::vector<std::list<Session>::iterator> done;
+        for (auto it = P->sessions.begin(); it != P->sessions.end(); ++it) {
+            if (it->phase != PH_INIT) continue;
+            try {
+                init_session(P, *it);
+                start_filter(P, *it);
+            } catch (const Error &e) {
+                it->r->error = afsi_last_error();
+                finish(P, *it, e.status, it->r->error);
+                done.push_back(it);
+            }
+        }
+        for (auto it : done) P->sessions.erase(it);
+        done.clear();
+        filt.clear();
+        groups.clear();
+        for (auto &s : P->sessions)
+            if (s.phase == PH_FILTER) {
+                afsi_step_group g{};
+                step_params(s.coeffs.data(), s.k_cur, s.step, s.l1, s.l2, &g);
+                g.col0 = s.col0;
+                g.ncols = round_up(s.p_act, P->E);
+                g.active = 1;
+                groups.push_back(g);
+                filt.push_back(&s);
+            }
+        try {
+            for (size_t g0 = 0; g0 < groups.size(); g0 += 64) {
+                const int ng = (int)std::min<size_t>(64, groups.size() - g0);
+                void **buf = P->mixed() ? P->F : P->B;
+                batched_step(P->A, ng, groups.data() + g0, P->fdt, buf[0], buf[1], buf[2], P->cap,
+                             P->cap, P->stream);
+                std::lock_guard<std::mutex> lk(S->mu);
+                ++S->launches;
+                S->launch_groups += ng;
+            }
+        } catch (const Error &e) {
+            const std::string msg = afsi_last_error();
+            for (auto *s : filt) s->phase = -1, finish(P, *s, e.status, msg);
+            P->sessions.remove_if([](const Session &s) { return s.phase == -1; });
+            continue;
+        }
+        for (auto *s : filt)
+            if (++s->step == s->k_cur) s->phase = PH_DENSE;
+        for (auto it = P->sessions.begin(); it != P->sessions.end(); ++it) {
+            if (it->phase != PH_DENSE) continue;
+            try {
+                const int outcome = dense_phase(P, *it);
+                if (outcome != DP_CONTINUE) {
+                    sort_results(P, it->r);
+                    finish(P, *it, outcome == DP_CONVERGED ? AFSI_OK : AFSI_E_NOCONV, "");
+                    done.push_back(it);
+                }
+            } catch (const Error &e) {
+                finish(P, *it, e.status, afsi_last_error());
+                done.push_back(it);
+            }
+        }
+        for (auto it : done) P->sessions.erase(it);
+    }
+}
+
+}  // namespace srv
+}  // namespace afsi
+
+struct afsi_server_s : afsi::srv::Server {};
+
+using namespace afsi;
+using namespace afsi::srv;
+
+extern "C" {
+
+int afsi_server_create(int device, int64_t hbm_budget_bytes, afsi_server_t *out) {
+    return guarded([&] {
+        AFSI_REQUIRE(out != nullptr && hbm_budget_bytes > 0, "bad argument");
+        DeviceGuard dg(device);
+        auto *S = new afsi_server_s();
+        S->device = device;
+        S->budget = hbm_budget_bytes;
+        *out = S;
+    });
+}
+
+int afsi_server_destroy(afsi_server_t S) {
+    return guarded([&] {
+        if (!S) return;
+        std::unique_lock<std::mutex> lk(S->mu);
+        S->stopping = true;
+        for (Request *r : S->queue) r->state = Q_FAILED, r->error = "server stopped";
+        S->queue.clear();
+        S->cv.wait(lk, [&] { return S->live_threads == 0; });
+        DeviceGuard dg(S->device);
+        for (auto &kv : S->reqs)
+            if (kv.second->evecs) (void)hipFree(kv.second->evecs);
+        lk.unlock();
+        delete S;
+    });
+}
+
+int afsi_server_set_pool_columns(afsi_server_t S, afsi_matrix_t A, int64_t cols) {
+    return guarded([&] {
+        AFSI_REQUIRE(S && A && cols > 0, "bad argument");
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->pool_cols[A] = cols;
+    });
+}
+
+int afsi_server_submit(afsi_server_t S, afsi_matrix_t A, double a, double b, int64_t p,
+                       const afsi_options *opts, uint64_t seed, int64_t *id) {
+    return guarded([&] {
+        AFSI_REQUIRE(S && A && opts && id, "NULL argument");
+        AFSI_REQUIRE(A->device == S->device, "matrix lives on another device");
+        AFSI_REQUIRE(A->has_bounds, "spectral bounds are not set on this matrix");
+        AFSI_REQUIRE(b > a && p >= 1 && p <= A->n, "need a < b and 1 <= p <= n");
+        AFSI_REQUIRE(opts->kmax >= 1 && opts->max_iter >= 1, "kmax and max_iter must be >= 1");
+        const int dt = A->dtype;
+        const int fdt = opts->filter_dtype;
+        AFSI_REQUIRE(fdt >= AFSI_R64 && fdt <= AFSI_C64 && is_complex(fdt) == is_complex(dt),
+                     "filter dtype must match the matrix domain");
+        std::unique_ptr<Request> r(new Request());
+        r->A = A;
+        r->a = a;
+        r->b = b;
+        r->p = p;
+        r->opts = *opts;
+        r->seed = seed;
+        r->dt = dt;
+        r->fdt = fdt;
+        r->evec_bytes = (size_t)A->n * p * elem_bytes(dt);
+        const size_t alone = pool_bytes(A->n, round_up(p, col_align(dt, fdt)), dt, fdt) + r->evec_bytes;
+        if ((int64_t)alone > S->budget)
+            AFSI_FAIL(AFSI_E_BUSY, "request needs %zu bytes, the budget is %lld", alone,
+                      (long long)S->budget);
+        std::lock_guard<std::mutex> lk(S->mu);
+        AFSI_REQUIRE(!S->stopping, "server is stopping");
+        r->id = S->next_id++;
+        r->t_submit = S->now();
+        *id = r->id;
+        S->queue.push_back(r.get());
+        S->reqs[r->id] = std::move(r);
+        try_admit(S);
+    });
+}
+
+static void fill_info(const Request *r, afsi_request_info *info) {
+    info->state = r->state;
+    info->status = r->status;
+    info->count = r->n_lock;
+    info->iterations = r->iterations;
+    info->converged = r->converged;
+    info->spmv = r->spmv;
+    info->avg_degree = r->avg_degree;
+    info->t_submit = r->t_submit;
+    info->t_admit = r->t_admit;
+    info->t_done = r->t_done;
+}
+
+int afsi_server_info(afsi_server_t S, int64_t id, afsi_request_info *info) {
+    return guarded([&] {
+        AFSI_REQUIRE(S && info, "NULL argument");
+        std::lock_guard<std::mutex> lk(S->mu);
+        auto it = S->reqs.find(id);
+        AFSI_REQUIRE(it != S->reqs.end(), "unknown request %lld", (long long)id);
+        fill_info(it->second.get(), info);
+    });
+}
+
+int afsi_server_wait(afsi_server_t S, int64_t id, double timeout_s, afsi_request_info *info) {
+    return guarded([&] {
+        AFSI_REQUIRE(S && info, "NULL argument");
+        std::unique_lock<std::mutex> lk(S->mu);
+        auto it = S->reqs.find(id);
+        AFSI_REQUIRE(it != S->reqs.end(), "unknown request %lld", (long long)id);
+        Request *r = it->second.get();
+        S->cv.wait_for(lk, std::chrono::duration<double>(timeout_s),
+                       [&] { return r->state >= Q_DONE; });
+        fill_info(r, info);
+    });
+}
+
+int afsi_server_wait_any(afsi_server_t S, double timeout_s, int64_t *id) {
+    return guarded([&] {
+        AFSI_REQUIRE(S && id, "NULL argument");
+        std::unique_lock<std::mutex> lk(S->mu);
+        S->cv.wait_for(lk, std::chrono::duration<double>(timeout_s),
+                       [&] { return !S->finished.empty(); });
+        if (S->finished.empty()) {
+            *id = -1;
+        } else {
+            *id = S->finished.front();
+            S->finished.pop_front();
+        }
+    });
+}
+
+int afsi_server_fetch(afsi_server_t S, int64_t id, double *eigenvalues, double *residuals,
+                      int64_t capacity, afsi_block *evecs, void *stream) {
+    return guarded([&] {
+        AFSI_REQUIRE(S, "NULL server");
+        std::unique_ptr<Request> r;
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            auto it = S->reqs.find(id);
+            AFSI_REQUIRE(it != S->reqs.end(), "unknown request %lld", (long long)id);
+            AFSI_REQUIRE(it->second->state >= Q_DONE, "request %lld has not finished", (long long)id);
+            AFSI_REQUIRE(capacity >= it->second->n_lock, "capacity %lld < %lld eigenpairs",
+                         (long long)capacity, (long long)it->second->n_lock);
+            if (evecs) {
+                AFSI_REQUIRE(evecs->dtype == it->second->dt && evecs->rows == it->second->A->n &&
+                                 evecs->cols >= it->second->n_lock,
+                             "evecs must be n x count of the matrix's FP64 dtype");
+            }
+            r = std::move(it->second);
+            S->reqs.erase(it);
+        }
+        const int64_t cnt = r->n_lock;
+        if (cnt) {
+            if (eigenvalues) std::memcpy(eigenvalues, r->lam.data(), sizeof(double) * cnt);
+            if (residuals) std::memcpy(residuals, r->res.data(), sizeof(double) * cnt);
+        }
+        DeviceGuard dg(S->device);
+        if (evecs && cnt && r->A->n) {
+            const int eb = elem_bytes(r->dt);
+            hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+            AFSI_HIP(hipMemcpy2DAsync(evecs->ptr, evecs->ld * eb, r->evecs, r->p * eb, cnt * eb,
+                                      r->A->n, hipMemcpyDeviceToDevice, s));
+            AFSI_HIP(hipStreamSynchronize(s));
+        }
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (r->evecs) {
+            (void)hipFree(r->evecs);
+            S->in_use -= (int64_t)r->evec_bytes;
+        }
+        try_admit(S);
+    });
+}
+
+int afsi_server_get_stats(afsi_server_t S, afsi_server_stats *st) {
+    return guarded([&] {
+        AFSI_REQUIRE(S && st, "NULL argument");
+        std::lock_guard<std::mutex> lk(S->mu);
+        st->bytes_in_use = S->in_use;
+        st->budget = S->budget;
+        st->queued = (int64_t)S->queue.size();
+        int64_t running = 0;
+        for (auto &kv : S->reqs) running += kv.second->state == Q_RUNNING;
+        st->running = running;
+        st->done = S->n_done;
+        st->pools = (int64_t)S->pools.size();
+        st->batched_launches = S->launches;
+        st->batched_groups = S->launch_groups;
+        st->now = S->now();
+    });
+}
+
+}  // extern "C"

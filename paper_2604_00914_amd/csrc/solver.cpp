@@ -34,17 +34,9 @@ double ms_since(clk::time_point t0) {
     return std::chrono::duration<double, std::milli>(clk::now() - t0).count();
 }
 
-// Gather columns `cols` of src (n x ?, ld) into dst columns [0, count) (ld): device kernel.
 void gather(int dtype, const void *src, int64_t n, int64_t ld, const std::vector<int32_t> &cols,
             void *dst, int64_t ldd, hipStream_t s) {
-    if (cols.empty() || n == 0) return;
-    afsi_block sb{const_cast<void *>(src), n, ld, ld, dtype};
-    afsi_block db{dst, n, (int64_t)cols.size(), ldd, dtype};
-    Workspace &ws = workspace(s);
-    int32_t *d = (int32_t *)ws.dev_reserve(SLOT_GATHER, sizeof(int32_t) * cols.size());
-    AFSI_HIP(hipMemcpyAsync(d, cols.data(), sizeof(int32_t) * cols.size(), hipMemcpyHostToDevice, s));
-    launch_gather_columns(sb, d, (int64_t)cols.size(), db, s);
-    AFSI_HIP(hipStreamSynchronize(s));  // the index list lives in reusable scratch
+    gather_cols(dtype, src, n, ld, cols.data(), (int64_t)cols.size(), dst, ldd, s);
 }
 
 // splitmix64 (Steele, Lea, Flood 2014) and Box-Muller normals for the Lanczos start vector

@@ -39,6 +39,39 @@ __global__ void scale_strided_kernel(double *__restrict__ x, int64_t n, int64_t 
 
 static unsigned blocks_for(int64_t count) { return (unsigned)((count + 255) / 256); }
 
+// splitmix64 finaliser (Steele, Lea, Flood 2014) used as a counter-based generator.
+__device__ inline uint64_t mix64(uint64_t z) {
+    z += 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+__device__ inline double unit_open(uint64_t r) { return ((r >> 11) + 0.5) * (1.0 / 9007199254740992.0); }
+
+// N(0,1) entries for element (i, j) of an n x p block, from counter (i * p + j): the
+// value depends only on (seed, i, j, p), not on where the block is stored.
+__global__ void fill_normal_kernel(double *__restrict__ x, int64_t n, int64_t p, int64_t ld,
+                                   int comp, uint64_t seed) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n * p) return;
+    const int64_t i = idx / p, j = idx % p;
+    const uint64_t base = mix64(seed) ^ (uint64_t)(idx * 4);
+    for (int c = 0; c < comp; ++c) {
+        const double u1 = unit_open(mix64(base + 2 * c)), u2 = unit_open(mix64(base + 2 * c + 1));
+        double g = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+        if (comp == 2) g *= 0.7071067811865476;
+        x[(i * ld + j) * comp + c] = g;
+    }
+}
+
+void launch_fill_normal(double *x, int64_t n, int64_t p, int64_t ld, int comp, uint64_t seed,
+                        hipStream_t st) {
+    if (n * p == 0) return;
+    hipLaunchKernelGGL(fill_normal_kernel, dim3((unsigned)((n * p + 255) / 256)), dim3(256), 0, st, x,
+                       n, p, ld, comp, seed);
+    AFSI_HIP(hipGetLastError());
+}
+
 // x[i * ld + 0..comp) *= s for i < n (one strided column; comp = 2 for complex).
 void launch_scale(double *x, int64_t n, int64_t ld, int comp, double s, hipStream_t st) {
     if (n == 0) return;
