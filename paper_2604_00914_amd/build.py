@@ -37,9 +37,32 @@ def sources():
     return sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
 
-def _compile(src: str, verbose: bool):
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc(), *COMMON, *DEVICE, "-c", os.path.join(CSRC, src), "-o", obj]
+# host-only sources (no HIP), built with the host compiler and OpenMP (libgomp):
+# source -> [(object, extra flags)]; host_linalg.cpp twice, generic and AVX2/FMA
+HOST_ONLY = {
+    "host_linalg.cpp": [("host_linalg_generic.o", ["-DAFSI_ISA_NS=generic"]),
+                        ("host_linalg_avx2.o", ["-DAFSI_ISA_NS=avx2", "-mavx2", "-mfma"])],
+    "host_linalg_dispatch.cpp": [("host_linalg_dispatch.o", [])],
+}
+HOST_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fcx-limited-range", "-fopenmp",
+              "-Wall"]
+
+
+def _jobs():
+    out = []
+    for src in sources():
+        for obj, extra in HOST_ONLY.get(src, [(os.path.splitext(src)[0] + ".o", None)]):
+            out.append((src, obj, extra))
+    return out
+
+
+def _compile(job, verbose: bool):
+    src, objname, extra = job
+    obj = os.path.join(BUILD, objname)
+    if extra is not None:
+        cmd = [os.environ.get("CXX", "g++"), *HOST_FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
+    else:
+        cmd = [hipcc(), *COMMON, *DEVICE, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     out = "\n".join(l for l in (r.stdout + r.stderr).splitlines() if "packed-fp32-ops" not in l)
     if r.returncode != 0:
@@ -53,9 +76,9 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     os.makedirs(BUILD, exist_ok=True)
     jobs = jobs or min(8, os.cpu_count() or 4)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), sources()))
+        objs = list(ex.map(lambda j: _compile(j, verbose), _jobs()))
     tmp = LIB + f".tmp{os.getpid()}"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-lgomp", "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"linking libafsi.so failed:\n{r.stdout}{r.stderr}")

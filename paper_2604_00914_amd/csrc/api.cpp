@@ -310,7 +310,7 @@ void rayleigh_ritz_dev(afsi_matrix_t A, int dtype, const void *Q, void *V, void 
     inner_dev(dtype, Q, ld, V, ld, n, p, p, B, p, s);      // B <- Q^H A Q
     AFSI_HIP(hipMemcpyAsync(Bh, B, mbytes, hipMemcpyDeviceToHost, s));
     AFSI_HIP(hipStreamSynchronize(s));
-    host_eigh(p, cplx, Bh, p, ritz, Uh, p);
+    host_eigh_or_throw(p, cplx, Bh, p, ritz, Uh, p);
     AFSI_HIP(hipMemcpyAsync(B, Uh, mbytes, hipMemcpyHostToDevice, s));
     gemm_dev(dtype, V, ld, B, p, n, p, p, 1.0, 0.0, AV, ld, s);  // AV <- (A Q) U
     gemm_dev(dtype, Q, ld, B, p, n, p, p, 1.0, 0.0, V, ld, s);   // V  <- Q U
@@ -789,9 +789,21 @@ int afsi_host_eigh(int64_t p, int32_t dtype, const double *B, int64_t ldb, doubl
         AFSI_REQUIRE(dtype == AFSI_R64 || dtype == AFSI_C128, "dtype must be R64 or C128");
         AFSI_REQUIRE(p >= 0 && ldb >= p && ldu >= p, "bad shape");
         AFSI_REQUIRE(p == 0 || (B && w && U), "NULL argument");
-        host_eigh(p, dtype == AFSI_C128, B, ldb, w, U, ldu);
+        host_eigh_or_throw(p, dtype == AFSI_C128, B, ldb, w, U, ldu);
     });
 }
+
+}  // extern "C"
+
+namespace afsi {
+void host_eigh_or_throw(int64_t p, bool cplx, const double *B, int64_t ldb, double *w, double *U,
+                        int64_t ldu) {
+    if (!host_eigh(p, cplx, B, ldb, w, U, ldu))
+        AFSI_FAIL(AFSI_E_HIP, "Hermitian eigensolver (tridiagonal QR) did not converge");
+}
+}  // namespace afsi
+
+extern "C" {
 
 int afsi_host_cholesky_inverse(int64_t p, int32_t dtype, double *G, int64_t ldg, double shift) {
     return guarded([&] {

@@ -1,13 +1,22 @@
 // Small dense Hermitian linear algebra on the host (FP64), p up to a few thousand.
+// Built with the host compiler and OpenMP (no HIP).
 //
 //  * host_cholesky_inverse: R^{-1} for the Cholesky factor R^H R = G + shift I, with
 //    symmetric diagonal scaling (G -> D G D, unit diagonal) before factoring; used by
-//    Cholesky QR, where only X R^{-1} is needed.
-//  * host_eigh: Hermitian eigendecomposition B = U diag(w) U^H.  Householder
-//    reduction to tridiagonal form (complex reflectors for Hermitian B), a diagonal
-//    unitary scaling that makes the off-diagonal real and non-negative, then the
-//    implicit symmetric QR iteration with Wilkinson shifts on the real tridiagonal
-//    (Golub & Van Loan, Matrix Computations, ch. 8.3), accumulating rotations.
+//    Cholesky QR, where only X R^{-1} is needed.  Right-looking factorisation and a
+//    row-oriented inverse: every inner loop is a contiguous axpy.
+//  * host_eigh: Hermitian eigendecomposition B = U diag(w) U^H (Golub & Van Loan,
+//    Matrix Computations, ch. 8.3): Householder reduction to tridiagonal form
+//    (complex reflectors for Hermitian B), a diagonal unitary scaling that makes the
+//    off-diagonal real, the implicit symmetric QR iteration with Wilkinson shifts on
+//    the real tridiagonal (its plane rotations recorded), then
+//    U = H_0 ... H_{p-3} diag(delta) Z.  Rotations and reflectors are applied to
+//    column chunks of the eigenvector matrix in parallel.
+//
+// Compiled twice (AFSI_ISA_NS = generic, and avx2 with -mavx2 -mfma); the entry
+// points in host_linalg_dispatch.cpp pick one at run time.
+#include "host_linalg.h"
+
 #include <algorithm>
 #include <cmath>
 #include <complex>
@@ -15,29 +24,49 @@
 #include <numeric>
 #include <vector>
 
-#include "internal.h"
+#ifndef AFSI_ISA_NS
+#define AFSI_ISA_NS generic
+#endif
 
 namespace afsi {
+namespace AFSI_ISA_NS {
 
 using cd = std::complex<double>;
 
-template <class T>
-static inline double absq(const T &x) { return std::norm(x); }
 static inline double absq(double x) { return x * x; }
+static inline double absq(const cd &x) { return std::norm(x); }
 static inline double conjv(double x) { return x; }
 static inline cd conjv(const cd &x) { return std::conj(x); }
 static inline double realv(double x) { return x; }
 static inline double realv(const cd &x) { return x.real(); }
 
+static const int64_t kParallelMin = 160;  // below this size threads cost more than they save
+static const int64_t kChunk = 32;         // columns per task when applying rotations / reflectors
+
+// sum_j a[j] * b[j] with four independent partial sums (fixed order, vectorisable)
+template <class T>
+static inline T dot4(const T *a, const T *b, int64_t m) {
+    T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
+    int64_t j = 0;
+    for (; j + 4 <= m; j += 4) {
+        s0 += a[j] * b[j];
+        s1 += a[j + 1] * b[j + 1];
+        s2 += a[j + 2] * b[j + 2];
+        s3 += a[j + 3] * b[j + 3];
+    }
+    for (; j < m; ++j) s0 += a[j] * b[j];
+    return (s0 + s1) + (s2 + s3);
+}
+
 template <class T>
 static bool chol_inv_impl(int64_t p, T *G, int64_t ld, double shift) {
-    // H = G + shift I, scaled to unit diagonal
     std::vector<double> dscale(p);
     for (int64_t i = 0; i < p; ++i) {
         const double h = realv(G[i * ld + i]) + shift;
         if (!(h > 0.0) || !std::isfinite(h)) return false;
         dscale[i] = 1.0 / std::sqrt(h);
     }
+    // H' = D (G + shift I) D, upper triangle, row-major p x p
     std::vector<T> R((size_t)p * p, T(0));
     for (int64_t i = 0; i < p; ++i)
         for (int64_t j = i; j < p; ++j) {
@@ -45,30 +74,37 @@ static bool chol_inv_impl(int64_t p, T *G, int64_t ld, double shift) {
             if (i == j) h = T(realv(h) + shift);
             R[i * p + j] = h * (dscale[i] * dscale[j]);
         }
-    // upper Cholesky in place: R^H R = H'
+    // right-looking upper Cholesky: finish row j, subtract its outer product from the
+    // trailing rows (upper part only)
     for (int64_t j = 0; j < p; ++j) {
-        double dj = realv(R[j * p + j]);
-        for (int64_t k = 0; k < j; ++k) dj -= absq(R[k * p + j]);
-        if (!(dj > 0.0) || !std::isfinite(dj)) return false;
-        const double rjj = std::sqrt(dj);
-        R[j * p + j] = T(rjj);
+        T *rj = &R[j * p];
+        const double d = realv(rj[j]);
+        if (!(d > 0.0) || !std::isfinite(d)) return false;
+        const double rjj = std::sqrt(d);
+        rj[j] = T(rjj);
+        const double inv = 1.0 / rjj;
+        for (int64_t l = j + 1; l < p; ++l) rj[l] *= inv;
         for (int64_t i = j + 1; i < p; ++i) {
-            T s = R[j * p + i];
-            for (int64_t k = 0; k < j; ++k) s -= conjv(R[k * p + j]) * R[k * p + i];
-            R[j * p + i] = s / rjj;
+            const T f = conjv(rj[i]);
+            T *ri = &R[i * p];
+            for (int64_t l = i; l < p; ++l) ri[l] -= f * rj[l];
         }
     }
-    // Z = R^{-1} (upper), column by column: R Z = I
+    // Z = R^{-1} row by row from the bottom: Z[i, :] = -(sum_{k>i} R[i, k] Z[k, :]) / R_ii
     std::vector<T> Z((size_t)p * p, T(0));
-    for (int64_t j = 0; j < p; ++j) {
-        Z[j * p + j] = T(1.0) / R[j * p + j];
-        for (int64_t i = j - 1; i >= 0; --i) {
-            T s = T(0);
-            for (int64_t k = i + 1; k <= j; ++k) s += R[i * p + k] * Z[k * p + j];
-            Z[i * p + j] = -s / R[i * p + i];
+    for (int64_t i = p - 1; i >= 0; --i) {
+        T *zi = &Z[i * p];
+        const T *ri = &R[i * p];
+        for (int64_t k = i + 1; k < p; ++k) {
+            const T f = ri[k];
+            const T *zk = &Z[k * p];
+            for (int64_t j = k; j < p; ++j) zi[j] += f * zk[j];
         }
+        const T inv = T(1.0) / ri[i];
+        for (int64_t j = i + 1; j < p; ++j) zi[j] *= -inv;
+        zi[i] = inv;
     }
-    // (D^{-1} R')^{-1} ... : H = D^{-1} R'^H R' D^{-1}, so R = R' D^{-1}, R^{-1} = D R'^{-1}
+    // R = R' D^{-1} with R'^H R' = H', so R^{-1} = D R'^{-1}
     for (int64_t i = 0; i < p; ++i)
         for (int64_t j = 0; j < p; ++j) G[i * ld + j] = j >= i ? Z[i * p + j] * dscale[i] : T(0);
     return true;
@@ -79,25 +115,29 @@ bool host_cholesky_inverse(int64_t p, bool cplx, double *G, int64_t ld, double s
     return chol_inv_impl<double>(p, G, ld, shift);
 }
 
-// Implicit symmetric tridiagonal QR with Wilkinson shift.  d[0..p), e[0..p-1).
-// Zt is p x p row-major holding Z^T (row k = k-th column of Z); rotations are
-// accumulated so that T_original = Z diag(d) Z^T on return.
-static void tridiag_qr(int64_t p, std::vector<double> &d, std::vector<double> &e,
-                       std::vector<double> &Zt) {
+struct Rot {
+    int64_t k;
+    double c, s;
+};
+
+// Implicit symmetric tridiagonal QR with Wilkinson shifts on d[0..p), e[0..p-1).
+// Each plane rotation J (T <- J T J^T on rows/columns k, k+1, J = [[c, s], [-s, c]])
+// is appended to `rots` in application order; T_original = Z diag(d) Z^T with
+// Z = J_1^T J_2^T ... .
+static bool tridiag_qr(int64_t p, std::vector<double> &d, std::vector<double> &e,
+                       std::vector<Rot> &rots) {
     const double eps = std::numeric_limits<double>::epsilon();
     int64_t iter = 0;
     const int64_t max_iter = 60 * std::max<int64_t>(p, 1);
     int64_t hi = p - 1;
     while (hi > 0) {
-        // deflate negligible off-diagonals
         for (int64_t i = 0; i < hi; ++i)
             if (std::fabs(e[i]) <= eps * (std::fabs(d[i]) + std::fabs(d[i + 1]))) e[i] = 0.0;
         while (hi > 0 && e[hi - 1] == 0.0) --hi;
         if (hi == 0) break;
         int64_t lo = hi - 1;
         while (lo > 0 && e[lo - 1] != 0.0) --lo;
-        if (++iter > max_iter) AFSI_FAIL(AFSI_E_HIP, "tridiagonal QR did not converge");
-        // Wilkinson shift from the trailing 2x2 block
+        if (++iter > max_iter) return false;
         const double delta = 0.5 * (d[hi - 1] - d[hi]);
         const double eb = e[hi - 1];
         const double den = delta + (delta >= 0 ? 1.0 : -1.0) * std::hypot(delta, eb);
@@ -117,23 +157,19 @@ static void tridiag_qr(int64_t p, std::vector<double> &d, std::vector<double> &e
                 e[k + 1] = c * e[k + 1];
                 x = e[k];
             }
-            double *zk = &Zt[k * p], *zk1 = &Zt[(k + 1) * p];
-            for (int64_t i = 0; i < p; ++i) {
-                const double u = zk[i], v = zk1[i];
-                zk[i] = c * u + s * v;
-                zk1[i] = -s * u + c * v;
-            }
+            rots.push_back({k, c, s});
         }
     }
+    return true;
 }
 
 template <class T>
-static void eigh_impl(int64_t p, const T *B, int64_t ldb, double *w, T *U, int64_t ldu) {
+static bool eigh_impl(int64_t p, const T *B, int64_t ldb, double *w, T *U, int64_t ldu) {
+    if (p == 0) return true;
     std::vector<T> A((size_t)p * p);
     for (int64_t i = 0; i < p; ++i)
         for (int64_t j = 0; j < p; ++j) A[i * p + j] = B[i * ldb + j];
-    // Hermitian part (inputs are Hermitian up to rounding)
-    for (int64_t i = 0; i < p; ++i) {
+    for (int64_t i = 0; i < p; ++i) {  // Hermitian part
         A[i * p + i] = T(realv(A[i * p + i]));
         for (int64_t j = i + 1; j < p; ++j) {
             const T h = 0.5 * (A[i * p + j] + conjv(A[j * p + i]));
@@ -141,56 +177,66 @@ static void eigh_impl(int64_t p, const T *B, int64_t ldb, double *w, T *U, int64
             A[j * p + i] = conjv(h);
         }
     }
-    std::vector<T> Q((size_t)p * p, T(0));
-    for (int64_t i = 0; i < p; ++i) Q[i * p + i] = T(1);
-    std::vector<T> v(p), u(p), wv(p);
-    // Householder reduction: column k below the diagonal -> alpha e_1
+    // Householder reduction; reflector k acts on indices k+1..p-1 with unit vector V[k].
+    // The reflector is formed by one thread; the symmetric product u = A_sub conj(v)...
+    // (u_i = sum_j A_ij v_j), and the rank-2 update A_sub -= v w^H + w v^H with
+    // w = 2u - 2 (v^H u) v, are shared by rows.
+    std::vector<std::vector<T>> V(p);
+    std::vector<T> u(p), wv(p), v(p);
+    bool skip = false;
+    T alpha = T(0);
+#pragma omp parallel if (p >= kParallelMin)
     for (int64_t k = 0; k + 2 < p; ++k) {
-        const int64_t m = p - k - 1;  // length of x = A[k+1:, k]
-        double xn2 = 0.0;
-        for (int64_t i = 0; i < m; ++i) xn2 += absq(A[(k + 1 + i) * p + k]);
-        const double xn = std::sqrt(xn2);
-        if (xn == 0.0) continue;
-        const T x0 = A[(k + 1) * p + k];
-        const double ax0 = std::sqrt(absq(x0));
-        const T phase = ax0 > 0 ? x0 / ax0 : T(1);
-        const T alpha = -phase * xn;
-        for (int64_t i = 0; i < m; ++i) v[i] = A[(k + 1 + i) * p + k];
-        v[0] -= alpha;
-        double vn2 = 0.0;
-        for (int64_t i = 0; i < m; ++i) vn2 += absq(v[i]);
-        const double vn = std::sqrt(vn2);
-        if (vn == 0.0) continue;
-        for (int64_t i = 0; i < m; ++i) v[i] /= vn;
-        // u = A_sub v, gamma = v^H u, w = 2u - 2 gamma v, A_sub -= v w^H + w v^H
-        for (int64_t i = 0; i < m; ++i) {
-            T s = T(0);
-            const T *ar = &A[(k + 1 + i) * p + k + 1];
-            for (int64_t j = 0; j < m; ++j) s += ar[j] * v[j];
-            u[i] = s;
+        const int64_t m = p - k - 1;
+#pragma omp single
+        {
+            double xn2 = 0.0;
+            for (int64_t i = 0; i < m; ++i) xn2 += absq(A[(k + 1 + i) * p + k]);
+            const double xn = std::sqrt(xn2);
+            skip = xn == 0.0;
+            if (!skip) {
+                const T x0 = A[(k + 1) * p + k];
+                const double ax0 = std::sqrt(absq(x0));
+                const T phase = ax0 > 0 ? x0 / ax0 : T(1);
+                alpha = -phase * xn;
+                for (int64_t i = 0; i < m; ++i) v[i] = A[(k + 1 + i) * p + k];
+                v[0] -= alpha;
+                double vn2 = 0.0;
+                for (int64_t i = 0; i < m; ++i) vn2 += absq(v[i]);
+                const double vn = std::sqrt(vn2);
+                skip = vn == 0.0;
+                if (!skip)
+                    for (int64_t i = 0; i < m; ++i) v[i] /= vn;
+            }
         }
-        T gamma = T(0);
-        for (int64_t i = 0; i < m; ++i) gamma += conjv(v[i]) * u[i];
-        const double g = realv(gamma);
-        for (int64_t i = 0; i < m; ++i) wv[i] = 2.0 * u[i] - 2.0 * g * v[i];
+        if (skip) continue;
+#pragma omp for schedule(static)
+        for (int64_t i = 0; i < m; ++i) u[i] = dot4(&A[(k + 1 + i) * p + k + 1], v.data(), m);
+#pragma omp single
+        {
+            T gamma = T(0);
+            for (int64_t i = 0; i < m; ++i) gamma += conjv(v[i]) * u[i];
+            const double g = realv(gamma);
+            for (int64_t i = 0; i < m; ++i) wv[i] = 2.0 * u[i] - 2.0 * g * v[i];
+            // conjugated copies make the row update a pair of plain axpys
+            for (int64_t i = 0; i < m; ++i) u[i] = conjv(wv[i]);
+        }
+#pragma omp for schedule(static)
         for (int64_t i = 0; i < m; ++i) {
             T *ar = &A[(k + 1 + i) * p + k + 1];
-            for (int64_t j = 0; j < m; ++j) ar[j] -= v[i] * conjv(wv[j]) + wv[i] * conjv(v[j]);
+            const T vi = v[i], wi = wv[i];
+            for (int64_t j = 0; j < m; ++j) ar[j] -= vi * u[j] + wi * conjv(v[j]);
         }
-        A[(k + 1) * p + k] = alpha;
-        A[k * p + k + 1] = conjv(alpha);
-        for (int64_t i = 1; i < m; ++i) A[(k + 1 + i) * p + k] = A[k * p + k + 1 + i] = T(0);
-        // Q <- Q H on columns k+1..p-1
-        for (int64_t r = 0; r < p; ++r) {
-            T *qr = &Q[r * p + k + 1];
-            T s = T(0);
-            for (int64_t j = 0; j < m; ++j) s += qr[j] * v[j];
-            s *= 2.0;
-            for (int64_t j = 0; j < m; ++j) qr[j] -= s * conjv(v[j]);
+#pragma omp single
+        {
+            A[(k + 1) * p + k] = alpha;
+            A[k * p + k + 1] = conjv(alpha);
+            for (int64_t i = 1; i < m; ++i) A[(k + 1 + i) * p + k] = A[k * p + k + 1 + i] = T(0);
+            V[k].assign(v.begin(), v.begin() + m);
         }
     }
     // real tridiagonal via phases delta_{k+1} = delta_k e_k / |e_k|
-    std::vector<double> d(p), e(p > 0 ? p - 1 : 0);
+    std::vector<double> d(p), e(p - 1);
     std::vector<T> delta(p, T(1));
     for (int64_t k = 0; k < p; ++k) d[k] = realv(A[k * p + k]);
     for (int64_t k = 0; k + 1 < p; ++k) {
@@ -199,35 +245,72 @@ static void eigh_impl(int64_t p, const T *B, int64_t ldb, double *w, T *U, int64
         e[k] = ae;
         delta[k + 1] = ae > 0 ? delta[k] * (ek / ae) : delta[k];
     }
-    std::vector<double> Zt((size_t)p * p, 0.0);
-    for (int64_t i = 0; i < p; ++i) Zt[i * p + i] = 1.0;
-    tridiag_qr(p, d, e, Zt);
+    std::vector<Rot> rots;
+    rots.reserve((size_t)2 * p * p);
+    if (!tridiag_qr(p, d, e, rots)) return false;
     std::vector<int64_t> order(p);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return d[a] < d[b]; });
-    // U = Q diag(delta) Z
-    std::vector<T> QD((size_t)p * p);
-    for (int64_t r = 0; r < p; ++r)
-        for (int64_t k = 0; k < p; ++k) QD[r * p + k] = Q[r * p + k] * delta[k];
-    for (int64_t jj = 0; jj < p; ++jj) {
-        const int64_t j = order[jj];
-        w[jj] = d[j];
-        const double *z = &Zt[j * p];
-        for (int64_t r = 0; r < p; ++r) {
-            const T *qd = &QD[r * p];
-            T s = T(0);
-            for (int64_t k = 0; k < p; ++k) s += qd[k] * z[k];
-            U[r * ldu + jj] = s;
+    // C = diag(delta) Z as a row-major p x p matrix.  Z = I J_1^T J_2^T ...: rotation
+    // (k, c, s) replaces columns (z_k, z_{k+1}) by (c z_k + s z_{k+1}, -s z_k + c z_{k+1});
+    // kept transposed (Zt row k = column k of Z) so each rotation is two row axpys,
+    // applied to independent column chunks in parallel.  Then the reflectors
+    // H_{p-3}, ..., H_0 act on rows k+1.. of C, again chunk by chunk.
+    std::vector<double> Zt((size_t)p * p, 0.0);
+    std::vector<T> C((size_t)p * p);
+    const int64_t nchunks = (p + kChunk - 1) / kChunk;
+#pragma omp parallel if (p >= kParallelMin / 2)
+    {
+#pragma omp for schedule(dynamic)
+        for (int64_t ch = 0; ch < nchunks; ++ch) {
+            const int64_t i0 = ch * kChunk, i1 = std::min(p, i0 + kChunk);
+            for (int64_t i = i0; i < i1; ++i) Zt[i * p + i] = 1.0;
+            for (const Rot &r : rots) {
+                double *zk = &Zt[r.k * p], *zk1 = &Zt[(r.k + 1) * p];
+                for (int64_t i = i0; i < i1; ++i) {
+                    const double a = zk[i], b = zk1[i];
+                    zk[i] = r.c * a + r.s * b;
+                    zk1[i] = -r.s * a + r.c * b;
+                }
+            }
+        }
+        // C[r][jj] = delta[r] * Z[r][order[jj]] = delta[r] * Zt[order[jj]][r]
+#pragma omp for schedule(static)
+        for (int64_t r = 0; r < p; ++r)
+            for (int64_t jj = 0; jj < p; ++jj) C[r * p + jj] = delta[r] * Zt[order[jj] * p + r];
+#pragma omp for schedule(dynamic)
+        for (int64_t ch = 0; ch < nchunks; ++ch) {
+            const int64_t j0 = ch * kChunk, j1 = std::min(p, j0 + kChunk), nc = j1 - j0;
+            std::vector<T> wrow(nc);
+            for (int64_t k = p - 3; k >= 0; --k) {
+                const std::vector<T> &vk = V[k];
+                if (vk.empty()) continue;
+                std::fill(wrow.begin(), wrow.end(), T(0));
+                for (size_t i = 0; i < vk.size(); ++i) {
+                    const T f = conjv(vk[i]);
+                    const T *cr = &C[(k + 1 + i) * p + j0];
+                    for (int64_t j = 0; j < nc; ++j) wrow[j] += f * cr[j];
+                }
+                for (size_t i = 0; i < vk.size(); ++i) {
+                    const T f = 2.0 * vk[i];
+                    T *cr = &C[(k + 1 + i) * p + j0];
+                    for (int64_t j = 0; j < nc; ++j) cr[j] -= f * wrow[j];
+                }
+            }
         }
     }
+    for (int64_t r = 0; r < p; ++r)
+        for (int64_t jj = 0; jj < p; ++jj) U[r * ldu + jj] = C[r * p + jj];
+    for (int64_t jj = 0; jj < p; ++jj) w[jj] = d[order[jj]];
+    return true;
 }
 
-void host_eigh(int64_t p, bool cplx, const double *B, int64_t ldb, double *w, double *U,
+bool host_eigh(int64_t p, bool cplx, const double *B, int64_t ldb, double *w, double *U,
                int64_t ldu) {
     if (cplx)
-        eigh_impl<cd>(p, reinterpret_cast<const cd *>(B), ldb, w, reinterpret_cast<cd *>(U), ldu);
-    else
-        eigh_impl<double>(p, B, ldb, w, U, ldu);
+        return eigh_impl<cd>(p, reinterpret_cast<const cd *>(B), ldb, w, reinterpret_cast<cd *>(U), ldu);
+    return eigh_impl<double>(p, B, ldb, w, U, ldu);
 }
 
+}  // namespace AFSI_ISA_NS
 }  // namespace afsi

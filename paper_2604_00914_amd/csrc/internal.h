@@ -9,6 +9,7 @@
 #include <string>
 
 #include "../../include/afsi.h"
+#include "host_linalg.h"
 
 namespace afsi {
 
@@ -205,13 +206,10 @@ void batched_step(afsi_matrix_t A, int ngroups, const afsi_step_group *groups, i
                   const void *X, void *P0, void *P1, int64_t ptot, int64_t ld, hipStream_t s);
 
 // ---------------------------------------------------------------- host linear algebra
-
-// Upper Cholesky of a Hermitian p x p matrix (row-major, ld), overwriting with
-// R^{-1} (upper).  Returns false on a non-positive pivot.  Column-scaled.
-bool host_cholesky_inverse(int64_t p, bool cplx, double *G, int64_t ld, double shift);
-// Hermitian eigensolver: w ascending, U (row-major p x p, ldu) unitary eigenvectors.
-void host_eigh(int64_t p, bool cplx, const double *B, int64_t ldb, double *w, double *U,
-               int64_t ldu);
+// host_cholesky_inverse, host_eigh: host_linalg.h (built without HIP, with OpenMP).
+// host_eigh_or_throw raises AFSI_E_HIP when the tridiagonal QR does not converge.
+void host_eigh_or_throw(int64_t p, bool cplx, const double *B, int64_t ldb, double *w, double *U,
+                        int64_t ldu);
 
 // ---------------------------------------------------------------- coefficients
 

@@ -307,7 +307,7 @@ int afsi_estimate_spectral_bounds(afsi_matrix_t A, int steps, uint64_t seed, voi
             T[(size_t)i * k + i] = alpha[i];
             if (i + 1 < k) T[(size_t)i * k + i + 1] = T[(size_t)(i + 1) * k + i] = beta[i];
         }
-        host_eigh(k, false, T.data(), k, th.data(), S.data(), k);
+        host_eigh_or_throw(k, false, T.data(), k, th.data(), S.data(), k);
         const double rlo = std::fabs(last_beta * S[(size_t)(k - 1) * k + 0]);
         const double rhi = std::fabs(last_beta * S[(size_t)(k - 1) * k + (k - 1)]);
         const double spread = th[k - 1] - th[0];
