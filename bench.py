@@ -82,6 +82,9 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run three plain device copies of one block (counter calibration)")
+    ap.add_argument("--sweep", default=None, metavar="OUT",
+                    help="only measure the filter alone on every workload and precision; "
+                         "one JSON line per case into OUT")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -98,6 +101,9 @@ def main():
         hipbuild.build()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.sweep:
+        filter_sweep(afsi, torch, dev, args.sweep)
+        return
 
     t0 = time.time()
     A, (lmin, lmax), (a, b), cfg = build_config(args.workload, size=args.size, seed=0)
@@ -144,8 +150,9 @@ def main():
             afsi.afsi_convert_block(F1, B1)
         steady_ms.extend(ms[2:][kind[2:] == 3].tolist())
 
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
     filt_ms = []
+    phase_ms = []    # (orthonormalize, Rayleigh-Ritz, residuals) per step
     n_check = [0]
 
     def step():
@@ -153,17 +160,22 @@ def main():
         run_filter(k)
         ev[1].record(stream)
         afsi.afsi_orthonormalize(None, B1, B2)
+        ev[2].record(stream)
         ritz = afsi.afsi_rayleigh_ritz(M.handle, B1, B0, B2)
+        ev[3].record(stream)
         res = afsi.afsi_residual_norms(B0, B2, ritz)
+        ev[4].record(stream)
         inside = (ritz >= a) & (ritz <= b)
         if inside.any():
             normA = max(abs(lmin), abs(lmax))
             _, _, _, n_check[0] = afsi.afsi_lock_select(ritz, res, inside, a, b, 1e-10 * normA, 0, n_check[0])
         filt_ms.append(ev[0].elapsed_time(ev[1]))
+        phase_ms.append([ev[i].elapsed_time(ev[i + 1]) for i in (1, 2, 3)])
 
     for w in range(max(args.warmup, 1)):
         step()
     filt_ms.clear()
+    phase_ms.clear()
     steady_ms.clear()
     torch.cuda.synchronize()
     log(f"warmup done; timing {args.steps} steps")
@@ -180,6 +192,19 @@ def main():
     filter_gbs = fbytes / (filt_med * 1e-3) / 1e9
     log(f"step {ms_per_step:.2f} ms, filter {filt_med:.2f} ms ({filter_gbs:.0f} GB/s), "
         f"dominant kernel {steady_launch_ms * 1e3:.1f} us avg over {len(steady_ms)} launches ({achieved:.0f} GB/s)")
+    orth_ms, rr_ms, res_ms = (float(v) for v in np.median(np.array(phase_ms), axis=0))
+
+    # measured copy bandwidth: a plain device copy of one block, same stream, HIP events
+    for _ in range(2):
+        B2.copy_(B1)
+    ev[0].record(stream)
+    for _ in range(10):
+        B2.copy_(B1)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * B1.numel() * B1.element_size() * 10 / (ev[0].elapsed_time(ev[1]) * 1e-3) / 1e9
+    log(f"phases: orthonormalize {orth_ms:.2f} ms, Rayleigh-Ritz {rr_ms:.2f} ms, residuals {res_ms:.2f} ms; "
+        f"device copy {copy_gbs:.0f} GB/s")
 
     traffic = None
     tpath = os.path.join(ROOT, "profiles", f"traffic_{cfg.name}_{args.form}.json")
@@ -212,6 +237,10 @@ def main():
         "pct_hbm_peak": round(100.0 * value / HBM_PEAK_GBS, 2),
         "filter_only_gbs": round(filter_gbs, 1),
         "filter_ms": round(filt_med, 3),
+        "phase_ms": {"filter": round(filt_med, 3), "orthonormalize": round(orth_ms, 3),
+                     "rayleigh_ritz": round(rr_ms, 3), "residuals": round(res_ms, 3)},
+        "measured_copy_gbs": round(copy_gbs, 1),
+        "dominant_frac_of_copy": round(achieved / copy_gbs, 4),
         "roofline": {
             "kernel": "clenshaw_step_kernel<HAS_V=1,HAS_X=1> (gather src, read V in place, read X, write V)",
             "launches": len(steady_ms),
@@ -235,6 +264,56 @@ def main():
         out["cpu_baseline"] = cpu_baseline(A, p, k, lmin, lmax, a, b, cfg, sx, args.cpu_sample_steps)
     M.close()
     print(json.dumps(out), flush=True)
+
+
+SWEEP = [("lap2d_64", "fp64"), ("lap3d_pot_100", "fp64"), ("lap3d_pot_100", "fp32"),
+         ("tb3d_64", "fp64"), ("tb3d_64", "fp32"), ("rand_2m", "fp32"), ("rand_2m", "fp64")]
+
+
+def filter_sweep(afsi, torch, dev, path, reps=3):
+    """Filter-only throughput of every workload in both precisions (inputs resident).
+
+    Per case: one warm-up filter, then `reps` filters, each product bracketed by HIP
+    events; reports the median filter time, its algorithmic GB/s and the steady
+    kernel's average launch time and GB/s.
+    """
+    from workloads import build_config, start_block
+
+    with open(path, "w") as fh:
+        for name, prec in SWEEP:
+            t0 = time.time()
+            A, (lmin, lmax), (a, b), cfg = build_config(name, seed=0)
+            n, p, k = A.n, cfg.p, cfg.degree
+            cplx = A.is_complex
+            M = afsi.Matrix(A, device=0, bounds=(lmin, lmax))
+            coeffs = afsi.afsi_filter_coefficients(lmin, lmax, a, b, k, cfg.damping)
+            dt = {("fp64", False): torch.float64, ("fp32", False): torch.float32,
+                  ("fp64", True): torch.complex128, ("fp32", True): torch.complex64}[(prec, cplx)]
+            X = torch.from_numpy(start_block(n, p, seed=0, complex_=cplx)).to(dev).to(dt)
+            Y, W = torch.empty_like(X), torch.empty_like(X)
+            sx = X.element_size()
+            fbytes, steady_bytes = filter_bytes(A.nnz, n, p, sx, sx, coeffs, k)
+            tot, steady = [], []
+            for r in range(reps + 1):
+                ms, kind = afsi.afsi_filter_block_profiled(M.handle, coeffs, k, X, Y, W)
+                if r:
+                    tot.append(float(np.sum(ms)))
+                    steady.extend(ms[2:][kind[2:] == 3].tolist())
+            fmed = float(np.median(tot))
+            sms = float(np.mean(steady))
+            rec = {"workload": name, "precision": prec, "dtype": str(dt).replace("torch.", ""),
+                   "n": n, "nnz": A.nnz, "p": p, "degree": k,
+                   "filter_ms": round(fmed, 3), "filter_gbs": round(fbytes / (fmed * 1e-3) / 1e9, 1),
+                   "steady_launch_us": round(sms * 1e3, 2),
+                   "steady_gbs": round(steady_bytes / (sms * 1e-3) / 1e9, 1),
+                   "steady_frac_hbm_peak": round(steady_bytes / (sms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                   "bytes_per_filter": fbytes, "bytes_per_steady_launch": steady_bytes}
+            log(f"sweep {name} {prec}: {rec} (setup {time.time() - t0:.1f}s)")
+            fh.write(json.dumps(rec) + "\n")
+            fh.flush()
+            del X, Y, W
+            M.close()
+            torch.cuda.empty_cache()
 
 
 def solve_rates(afsi, torch, dev):

@@ -24,6 +24,9 @@ COMMON = [
 ]
 # gfx950 device code: no packed FP32 instructions
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# per-source device flags: MFMA accumulators in ordinary VGPRs, so the k-loop carries
+# them without copies to and from the accumulator registers
+DEVICE_EXTRA = {"mfma_f64.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def hipcc() -> str:
@@ -62,7 +65,8 @@ def _compile(job, verbose: bool):
     if extra is not None:
         cmd = [os.environ.get("CXX", "g++"), *HOST_FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     else:
-        cmd = [hipcc(), *COMMON, *DEVICE, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [hipcc(), *COMMON, *DEVICE, *DEVICE_EXTRA.get(src, []), "-c", os.path.join(CSRC, src),
+               "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     out = "\n".join(l for l in (r.stdout + r.stderr).splitlines() if "packed-fp32-ops" not in l)
     if r.returncode != 0:

@@ -227,11 +227,11 @@ void inner_dev(int dtype, const void *X, int64_t ldx, const void *Y, int64_t ldy
 
 void gemm_dev(int dtype, const void *X, int64_t ldx, const double *M, int64_t ldm, int64_t n,
               int64_t p, int64_t q, double alpha, double beta, void *Y, int64_t ldy,
-              hipStream_t s) {
+              hipStream_t s, bool upper) {
     if (dtype == AFSI_C128)
-        gemm_c128((const double *)X, ldx, M, ldm, n, p, q, alpha, beta, (double *)Y, ldy, s);
+        gemm_c128((const double *)X, ldx, M, ldm, n, p, q, alpha, beta, (double *)Y, ldy, s, upper);
     else
-        gemm_f64((const double *)X, ldx, M, ldm, n, p, q, alpha, beta, (double *)Y, ldy, s);
+        gemm_f64((const double *)X, ldx, M, ldm, n, p, q, alpha, beta, (double *)Y, ldy, s, upper);
 }
 
 // X <- X - L (L^H X), twice.  L: n x k (ld ldl), X: n x p (ld ldx).
@@ -285,7 +285,7 @@ void orthonormalize_dev(int dtype, void *X, void *W, int64_t n, int64_t p, int64
             plain_passes = 0;
         }
         AFSI_HIP(hipMemcpyAsync(G, Gh, gbytes, hipMemcpyHostToDevice, s));
-        gemm_dev(dtype, cur, ld, G, p, n, p, p, 1.0, 0.0, oth, ld, s);
+        gemm_dev(dtype, cur, ld, G, p, n, p, p, 1.0, 0.0, oth, ld, s, true);  // X R^{-1}
         std::swap(cur, oth);
     }
     if (cur != X) {

@@ -20,6 +20,8 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <cstdlib>
+#include <new>
 #include <limits>
 #include <numeric>
 #include <vector>
@@ -42,6 +44,34 @@ static inline double realv(const cd &x) { return x.real(); }
 
 static const int64_t kParallelMin = 160;  // below this size threads cost more than they save
 static const int64_t kChunk = 32;         // columns per task when applying rotations / reflectors
+
+// Row-major scratch matrix whose rows start on 64-byte cache lines, so that column
+// chunks owned by different threads never share a line (a shared line would move
+// between cores on every rotation).
+template <class T>
+struct LineMatrix {
+    int64_t ld = 0;
+    T *data = nullptr;
+    LineMatrix(int64_t rows, int64_t cols) {
+        const int64_t per_line = 64 / (int64_t)sizeof(T);
+        ld = (cols + per_line - 1) / per_line * per_line;
+        const size_t bytes = (size_t)std::max<int64_t>(rows * ld, 1) * sizeof(T);
+        data = static_cast<T *>(std::aligned_alloc(64, (bytes + 63) / 64 * 64));
+        if (!data) throw std::bad_alloc();
+        std::fill(data, data + rows * ld, T(0));
+    }
+    ~LineMatrix() { std::free(data); }
+    LineMatrix(const LineMatrix &) = delete;
+    LineMatrix &operator=(const LineMatrix &) = delete;
+    T *row(int64_t r) { return data + r * ld; }
+};
+
+// sqrt(x^2 + z^2) without the cost of std::hypot when no scaling is needed
+static inline double fast_hypot(double x, double z) {
+    const double s = x * x + z * z;
+    if (s > 1e-290 && s < 1e290) return std::sqrt(s);
+    return std::hypot(x, z);
+}
 
 // sum_j a[j] * b[j] with four independent partial sums (fixed order, vectorisable)
 template <class T>
@@ -140,11 +170,11 @@ static bool tridiag_qr(int64_t p, std::vector<double> &d, std::vector<double> &e
         if (++iter > max_iter) return false;
         const double delta = 0.5 * (d[hi - 1] - d[hi]);
         const double eb = e[hi - 1];
-        const double den = delta + (delta >= 0 ? 1.0 : -1.0) * std::hypot(delta, eb);
+        const double den = delta + (delta >= 0 ? 1.0 : -1.0) * fast_hypot(delta, eb);
         const double mu = den != 0.0 ? d[hi] - eb * eb / den : d[hi];
         double x = d[lo] - mu, z = e[lo];
         for (int64_t k = lo; k < hi; ++k) {
-            const double r = std::hypot(x, z);
+            const double r = fast_hypot(x, z);
             double c = 1.0, s = 0.0;
             if (r != 0.0) c = x / r, s = z / r;
             if (k > lo) e[k - 1] = r;
@@ -256,28 +286,30 @@ static bool eigh_impl(int64_t p, const T *B, int64_t ldb, double *w, T *U, int64
     // kept transposed (Zt row k = column k of Z) so each rotation is two row axpys,
     // applied to independent column chunks in parallel.  Then the reflectors
     // H_{p-3}, ..., H_0 act on rows k+1.. of C, again chunk by chunk.
-    std::vector<double> Zt((size_t)p * p, 0.0);
-    std::vector<T> C((size_t)p * p);
+    LineMatrix<double> Zt(p, p);
+    LineMatrix<T> C(p, p);
     const int64_t nchunks = (p + kChunk - 1) / kChunk;
 #pragma omp parallel if (p >= kParallelMin / 2)
     {
 #pragma omp for schedule(dynamic)
         for (int64_t ch = 0; ch < nchunks; ++ch) {
             const int64_t i0 = ch * kChunk, i1 = std::min(p, i0 + kChunk);
-            for (int64_t i = i0; i < i1; ++i) Zt[i * p + i] = 1.0;
+            for (int64_t i = i0; i < i1; ++i) Zt.row(i)[i] = 1.0;
             for (const Rot &r : rots) {
-                double *zk = &Zt[r.k * p], *zk1 = &Zt[(r.k + 1) * p];
+                double *__restrict__ zk = Zt.row(r.k);
+                double *__restrict__ zk1 = Zt.row(r.k + 1);
+                const double c = r.c, s = r.s;
                 for (int64_t i = i0; i < i1; ++i) {
                     const double a = zk[i], b = zk1[i];
-                    zk[i] = r.c * a + r.s * b;
-                    zk1[i] = -r.s * a + r.c * b;
+                    zk[i] = c * a + s * b;
+                    zk1[i] = -s * a + c * b;
                 }
             }
         }
         // C[r][jj] = delta[r] * Z[r][order[jj]] = delta[r] * Zt[order[jj]][r]
 #pragma omp for schedule(static)
         for (int64_t r = 0; r < p; ++r)
-            for (int64_t jj = 0; jj < p; ++jj) C[r * p + jj] = delta[r] * Zt[order[jj] * p + r];
+            for (int64_t jj = 0; jj < p; ++jj) C.row(r)[jj] = delta[r] * Zt.row(order[jj])[r];
 #pragma omp for schedule(dynamic)
         for (int64_t ch = 0; ch < nchunks; ++ch) {
             const int64_t j0 = ch * kChunk, j1 = std::min(p, j0 + kChunk), nc = j1 - j0;
@@ -288,19 +320,19 @@ static bool eigh_impl(int64_t p, const T *B, int64_t ldb, double *w, T *U, int64
                 std::fill(wrow.begin(), wrow.end(), T(0));
                 for (size_t i = 0; i < vk.size(); ++i) {
                     const T f = conjv(vk[i]);
-                    const T *cr = &C[(k + 1 + i) * p + j0];
+                    const T *cr = C.row(k + 1 + i) + j0;
                     for (int64_t j = 0; j < nc; ++j) wrow[j] += f * cr[j];
                 }
                 for (size_t i = 0; i < vk.size(); ++i) {
                     const T f = 2.0 * vk[i];
-                    T *cr = &C[(k + 1 + i) * p + j0];
+                    T *cr = C.row(k + 1 + i) + j0;
                     for (int64_t j = 0; j < nc; ++j) cr[j] -= f * wrow[j];
                 }
             }
         }
     }
     for (int64_t r = 0; r < p; ++r)
-        for (int64_t jj = 0; jj < p; ++jj) U[r * ldu + jj] = C[r * p + jj];
+        for (int64_t jj = 0; jj < p; ++jj) U[r * ldu + jj] = C.row(r)[jj];
     for (int64_t jj = 0; jj < p; ++jj) w[jj] = d[order[jj]];
     return true;
 }

@@ -156,17 +156,21 @@ void launch_to_f32(const double *src, float *dst, int64_t count, hipStream_t s);
 
 // ---------------------------------------------------------------- kernels (dense.hip)
 
-// Real FP64: G (p x q, ldg) = X^T Y; scratch from workspace.
+// Real FP64: G (p x q, ldg) = X^T Y; scratch from workspace.  X == Y (same ld, p == q)
+// takes the symmetric path: upper tiles only, lower triangle mirrored.
 void gram_f64(const double *X, int64_t ldx, const double *Y, int64_t ldy, int64_t n, int64_t p,
               int64_t q, double *G, int64_t ldg, hipStream_t s);
-// Real FP64: Y = alpha X M + beta Y.
+// Real FP64: Y = alpha X M + beta Y.  upper: M is upper triangular (zeros below the
+// diagonal are skipped, not read).
 void gemm_f64(const double *X, int64_t ldx, const double *M, int64_t ldm, int64_t n, int64_t p,
-              int64_t q, double alpha, double beta, double *Y, int64_t ldy, hipStream_t s);
+              int64_t q, double alpha, double beta, double *Y, int64_t ldy, hipStream_t s,
+              bool upper = false);
 // Complex via real views.
 void gram_c128(const double *X, int64_t ldx, const double *Y, int64_t ldy, int64_t n, int64_t p,
                int64_t q, double *G, int64_t ldg, hipStream_t s);
 void gemm_c128(const double *X, int64_t ldx, const double *M, int64_t ldm, int64_t n, int64_t p,
-               int64_t q, double alpha, double beta, double *Y, int64_t ldy, hipStream_t s);
+               int64_t q, double alpha, double beta, double *Y, int64_t ldy, hipStream_t s,
+               bool upper = false);
 // norms[j] = || AV[:, j] - lambda[j] V[:, j] ||_2, device output (q doubles).
 void residual_norms_dev(int dtype, const void *V, int64_t ldv, const void *AV, int64_t ldav,
                         const double *d_lambda, int64_t n, int64_t q, double *d_norms,
@@ -185,7 +189,8 @@ void spmm_apply(afsi_matrix_t A, int dtype, const void *X, void *Y, int64_t p, i
 void inner_dev(int dtype, const void *X, int64_t ldx, const void *Y, int64_t ldy, int64_t n,
                int64_t p, int64_t q, double *G, int64_t ldg, hipStream_t s);
 void gemm_dev(int dtype, const void *X, int64_t ldx, const double *M, int64_t ldm, int64_t n,
-              int64_t p, int64_t q, double alpha, double beta, void *Y, int64_t ldy, hipStream_t s);
+              int64_t p, int64_t q, double alpha, double beta, void *Y, int64_t ldy, hipStream_t s,
+              bool upper = false);
 void project_out_dev(int dtype, const void *L, int64_t ldl, int64_t k, void *X, int64_t ldx,
                      int64_t n, int64_t p, hipStream_t s);
 void orthonormalize_dev(int dtype, void *X, void *W, int64_t n, int64_t p, int64_t ld,

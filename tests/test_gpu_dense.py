@@ -29,6 +29,22 @@ def test_block_inner(n, p, q, cplx):
 
 
 @pytest.mark.parametrize("cplx", [False, True])
+@pytest.mark.parametrize("n,p", [(1, 1), (7, 5), (1001, 70), (20000, 256), (3000, 300)])
+def test_block_inner_same_block_is_exactly_hermitian(n, p, cplx):
+    """X^H X through the symmetric path (one block passed twice): upper tiles only,
+    lower triangle mirrored; must match X^H X and be exactly Hermitian."""
+    t = torch()
+    X = _rand(n, p, cplx, 11)
+    Xd = to_dev(X)
+    G = t.empty((p, p), dtype=t.complex128 if cplx else t.float64, device=DEV)
+    afsi.afsi_block_inner(Xd, Xd, G)
+    got = G.cpu().numpy()
+    ref = X.conj().T @ X
+    assert np.max(np.abs(got - ref)) <= 1e-13 * np.sqrt(n) * max(1.0, np.abs(ref).max())
+    assert np.array_equal(got, got.conj().T)
+
+
+@pytest.mark.parametrize("cplx", [False, True])
 @pytest.mark.parametrize("n,p,q,beta", [(1, 1, 1, 0.0), (1001, 17, 70, 0.0), (5000, 64, 64, 1.0), (3000, 256, 250, -0.5)])
 def test_block_gemm(n, p, q, beta, cplx):
     t = torch()
@@ -40,9 +56,11 @@ def test_block_gemm(n, p, q, beta, cplx):
 
 
 @pytest.mark.parametrize("cplx", [False, True])
-def test_orthonormalize_with_locked(cplx):
+@pytest.mark.parametrize("p", [48, 200, 300])
+def test_orthonormalize_with_locked(cplx, p):
+    """p > 128 spans several column tiles of the triangular X R^{-1} product."""
     t = torch()
-    n, p, k = 3000, 48, 10
+    n, k = 3000, 10
     L, _ = np.linalg.qr(_rand(n, k, cplx, 6))
     X0 = _rand(n, p, cplx, 7)
     X = to_dev(X0)
