@@ -43,6 +43,9 @@ static inline double realv(double x) { return x; }
 static inline double realv(const cd &x) { return x.real(); }
 
 static const int64_t kParallelMin = 160;  // below this size threads cost more than they save
+// the Householder reduction synchronises its threads several times per column, which
+// only pays for larger matrices (size in real units: a complex p counts 2p)
+static const int64_t kHouseholderParallelMin = 320;
 static const int64_t kChunk = 32;         // columns per task when applying rotations / reflectors
 
 // Row-major scratch matrix whose rows start on 64-byte cache lines, so that column
@@ -73,19 +76,21 @@ static inline double fast_hypot(double x, double z) {
     return std::hypot(x, z);
 }
 
-// sum_j a[j] * b[j] with four independent partial sums (fixed order, vectorisable)
+// sum_j a[j] * b[j] with kDotLanes independent partial sums, added in a fixed order
+// at the end: the lanes map onto packed registers, so the loop vectorises without
+// reassociation
+static const int kDotLanes = 16;
 template <class T>
-static inline T dot4(const T *a, const T *b, int64_t m) {
-    T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
+static inline T dot_lanes(const T *a, const T *b, int64_t m) {
+    T acc[kDotLanes];
+    for (int t = 0; t < kDotLanes; ++t) acc[t] = T(0);
     int64_t j = 0;
-    for (; j + 4 <= m; j += 4) {
-        s0 += a[j] * b[j];
-        s1 += a[j + 1] * b[j + 1];
-        s2 += a[j + 2] * b[j + 2];
-        s3 += a[j + 3] * b[j + 3];
-    }
-    for (; j < m; ++j) s0 += a[j] * b[j];
-    return (s0 + s1) + (s2 + s3);
+    for (; j + kDotLanes <= m; j += kDotLanes)
+        for (int t = 0; t < kDotLanes; ++t) acc[t] += a[j + t] * b[j + t];
+    for (int t = 0; j < m; ++j, ++t) acc[t] += a[j] * b[j];
+    for (int w = kDotLanes / 2; w > 0; w /= 2)
+        for (int t = 0; t < w; ++t) acc[t] += acc[t + w];
+    return acc[0];
 }
 
 template <class T>
@@ -176,7 +181,11 @@ static bool tridiag_qr(int64_t p, std::vector<double> &d, std::vector<double> &e
         for (int64_t k = lo; k < hi; ++k) {
             const double r = fast_hypot(x, z);
             double c = 1.0, s = 0.0;
-            if (r != 0.0) c = x / r, s = z / r;
+            if (r != 0.0) {
+                const double rinv = 1.0 / r;
+                c = x * rinv;
+                s = z * rinv;
+            }
             if (k > lo) e[k - 1] = r;
             const double a = d[k], b = e[k], cc = d[k + 1];
             d[k] = c * c * a + 2.0 * c * s * b + s * s * cc;
@@ -191,6 +200,93 @@ static bool tridiag_qr(int64_t p, std::vector<double> &d, std::vector<double> &e
         }
     }
     return true;
+}
+
+// Applies the recorded rotations, in order, to columns [i0, i0 + width) of Zt (W > 0:
+// width == W, known at compile time).  The rotations of one QR sweep act on rows
+// (k, k+1), (k+1, k+2), ...: the row they share stays in `carry`, so each rotation
+// reads one row and writes one instead of two and two.
+template <int W>
+static void rotate_columns(LineMatrix<double> &Zt, const std::vector<Rot> &rots, int64_t i0,
+                           int64_t width) {
+    constexpr int kMax = W > 0 ? W : kChunk;
+    const int64_t nw = W > 0 ? W : width;
+    double carry[kMax];
+    int64_t held = -1;  // row whose current values are in carry (memory copy is stale)
+    for (const Rot &r : rots) {
+        if (r.k != held) {
+            if (held >= 0) {
+                double *zh = Zt.row(held) + i0;
+                for (int64_t i = 0; i < nw; ++i) zh[i] = carry[i];
+            }
+            const double *zk = Zt.row(r.k) + i0;
+            for (int64_t i = 0; i < nw; ++i) carry[i] = zk[i];
+        }
+        double *__restrict__ zk = Zt.row(r.k) + i0;
+        const double *__restrict__ zn = Zt.row(r.k + 1) + i0;
+        const double c = r.c, s = r.s;
+        for (int64_t i = 0; i < nw; ++i) {
+            const double a = carry[i], b = zn[i];
+            zk[i] = c * a + s * b;
+            carry[i] = -s * a + c * b;
+        }
+        held = r.k + 1;
+    }
+    if (held >= 0) {
+        double *zh = Zt.row(held) + i0;
+        for (int64_t i = 0; i < nw; ++i) zh[i] = carry[i];
+    }
+}
+
+// Consecutive Householder reflectors H_k = I - 2 v_k v_k^H (v_k unit, acting on
+// indices k+1..p-1; an empty v_k is the identity) grouped as
+//   H_k0 H_k0+1 ... H_k0+cnt-1 = I - Vb T Vb^H
+// (Schreiber & Van Loan's compact WY form): Vb holds v_k0+l in column l over rows
+// k0+1..p-1 (row-major, zero above each vector's first row), T is cnt x cnt upper
+// triangular with T_ll = tau_l and T[0:l, l] = -tau_l T[0:l, 0:l] (Vb[:, 0:l]^H v_l).
+static const int64_t kReflBlock = 16;
+
+template <class T>
+struct ReflBlock {
+    int64_t k0 = 0, cnt = 0;
+    std::vector<T> V, Tm;  // Vb (rows x cnt, row-major), T (cnt x cnt, row-major)
+};
+
+template <class T>
+static std::vector<ReflBlock<T>> reflector_blocks(int64_t p, const std::vector<std::vector<T>> &Vs) {
+    std::vector<ReflBlock<T>> out;
+    const int64_t nref = std::max<int64_t>(p - 2, 0);
+    for (int64_t k0 = 0; k0 < nref; k0 += kReflBlock) {
+        ReflBlock<T> rb;
+        rb.k0 = k0;
+        rb.cnt = std::min(kReflBlock, nref - k0);
+        const int64_t cnt = rb.cnt, rows = p - k0 - 1;
+        rb.V.assign((size_t)rows * cnt, T(0));
+        std::vector<double> tau(cnt);
+        for (int64_t l = 0; l < cnt; ++l) {
+            const std::vector<T> &v = Vs[k0 + l];
+            tau[l] = v.empty() ? 0.0 : 2.0;
+            for (size_t i = 0; i < v.size(); ++i) rb.V[(size_t)(l + i) * cnt + l] = v[i];
+        }
+        rb.Tm.assign((size_t)cnt * cnt, T(0));
+        std::vector<T> sv(cnt);
+        for (int64_t l = 0; l < cnt; ++l) {
+            for (int64_t m = 0; m < l; ++m) {
+                T acc = T(0);
+                for (int64_t r = l; r < rows; ++r)
+                    acc += conjv(rb.V[(size_t)r * cnt + m]) * rb.V[(size_t)r * cnt + l];
+                sv[m] = acc;
+            }
+            for (int64_t m = 0; m < l; ++m) {
+                T acc = T(0);
+                for (int64_t q = m; q < l; ++q) acc += rb.Tm[(size_t)m * cnt + q] * sv[q];
+                rb.Tm[(size_t)m * cnt + l] = -tau[l] * acc;
+            }
+            rb.Tm[(size_t)l * cnt + l] = T(tau[l]);
+        }
+        out.push_back(std::move(rb));
+    }
+    return out;
 }
 
 template <class T>
@@ -215,7 +311,9 @@ static bool eigh_impl(int64_t p, const T *B, int64_t ldb, double *w, T *U, int64
     std::vector<T> u(p), wv(p), v(p);
     bool skip = false;
     T alpha = T(0);
-#pragma omp parallel if (p >= kParallelMin)
+    const bool householder_threads =
+        p * (int64_t)(sizeof(T) / sizeof(double)) >= kHouseholderParallelMin;
+#pragma omp parallel if (householder_threads)
     for (int64_t k = 0; k + 2 < p; ++k) {
         const int64_t m = p - k - 1;
 #pragma omp single
@@ -241,7 +339,7 @@ static bool eigh_impl(int64_t p, const T *B, int64_t ldb, double *w, T *U, int64
         }
         if (skip) continue;
 #pragma omp for schedule(static)
-        for (int64_t i = 0; i < m; ++i) u[i] = dot4(&A[(k + 1 + i) * p + k + 1], v.data(), m);
+        for (int64_t i = 0; i < m; ++i) u[i] = dot_lanes(&A[(k + 1 + i) * p + k + 1], v.data(), m);
 #pragma omp single
         {
             T gamma = T(0);
@@ -285,26 +383,22 @@ static bool eigh_impl(int64_t p, const T *B, int64_t ldb, double *w, T *U, int64
     // (k, c, s) replaces columns (z_k, z_{k+1}) by (c z_k + s z_{k+1}, -s z_k + c z_{k+1});
     // kept transposed (Zt row k = column k of Z) so each rotation is two row axpys,
     // applied to independent column chunks in parallel.  Then the reflectors
-    // H_{p-3}, ..., H_0 act on rows k+1.. of C, again chunk by chunk.
+    // H_{p-3}, ..., H_0 act on rows k+1.. of C, again chunk by chunk, kReflBlock at a
+    // time in the compact form I - Vb T Vb^H.
     LineMatrix<double> Zt(p, p);
     LineMatrix<T> C(p, p);
     const int64_t nchunks = (p + kChunk - 1) / kChunk;
+    const std::vector<ReflBlock<T>> blocks = reflector_blocks(p, V);
 #pragma omp parallel if (p >= kParallelMin / 2)
     {
 #pragma omp for schedule(dynamic)
         for (int64_t ch = 0; ch < nchunks; ++ch) {
             const int64_t i0 = ch * kChunk, i1 = std::min(p, i0 + kChunk);
             for (int64_t i = i0; i < i1; ++i) Zt.row(i)[i] = 1.0;
-            for (const Rot &r : rots) {
-                double *__restrict__ zk = Zt.row(r.k);
-                double *__restrict__ zk1 = Zt.row(r.k + 1);
-                const double c = r.c, s = r.s;
-                for (int64_t i = i0; i < i1; ++i) {
-                    const double a = zk[i], b = zk1[i];
-                    zk[i] = c * a + s * b;
-                    zk1[i] = -s * a + c * b;
-                }
-            }
+            if (i1 - i0 == kChunk)
+                rotate_columns<kChunk>(Zt, rots, i0, kChunk);
+            else
+                rotate_columns<0>(Zt, rots, i0, i1 - i0);
         }
         // C[r][jj] = delta[r] * Z[r][order[jj]] = delta[r] * Zt[order[jj]][r]
 #pragma omp for schedule(static)
@@ -313,20 +407,40 @@ static bool eigh_impl(int64_t p, const T *B, int64_t ldb, double *w, T *U, int64
 #pragma omp for schedule(dynamic)
         for (int64_t ch = 0; ch < nchunks; ++ch) {
             const int64_t j0 = ch * kChunk, j1 = std::min(p, j0 + kChunk), nc = j1 - j0;
-            std::vector<T> wrow(nc);
-            for (int64_t k = p - 3; k >= 0; --k) {
-                const std::vector<T> &vk = V[k];
-                if (vk.empty()) continue;
-                std::fill(wrow.begin(), wrow.end(), T(0));
-                for (size_t i = 0; i < vk.size(); ++i) {
-                    const T f = conjv(vk[i]);
-                    const T *cr = C.row(k + 1 + i) + j0;
-                    for (int64_t j = 0; j < nc; ++j) wrow[j] += f * cr[j];
+            std::vector<T> W((size_t)kReflBlock * kChunk), W2((size_t)kReflBlock * kChunk);
+            for (int64_t b = (int64_t)blocks.size() - 1; b >= 0; --b) {
+                const ReflBlock<T> &rb = blocks[b];
+                const int64_t cnt = rb.cnt, r0 = rb.k0 + 1;
+                // W = Vb^H C[r0.., chunk]
+                std::fill(W.begin(), W.begin() + cnt * nc, T(0));
+                for (int64_t r = r0; r < p; ++r) {
+                    const T *cr = C.row(r) + j0;
+                    const T *vr = &rb.V[(size_t)(r - r0) * cnt];
+                    for (int64_t l = 0; l < cnt; ++l) {
+                        const T f = conjv(vr[l]);
+                        T *wl = &W[(size_t)l * nc];
+                        for (int64_t j = 0; j < nc; ++j) wl[j] += f * cr[j];
+                    }
                 }
-                for (size_t i = 0; i < vk.size(); ++i) {
-                    const T f = 2.0 * vk[i];
-                    T *cr = C.row(k + 1 + i) + j0;
-                    for (int64_t j = 0; j < nc; ++j) cr[j] -= f * wrow[j];
+                // W2 = T W (T upper triangular)
+                for (int64_t l = 0; l < cnt; ++l) {
+                    T *w2 = &W2[(size_t)l * nc];
+                    std::fill(w2, w2 + nc, T(0));
+                    for (int64_t m = l; m < cnt; ++m) {
+                        const T t = rb.Tm[(size_t)l * cnt + m];
+                        const T *wm = &W[(size_t)m * nc];
+                        for (int64_t j = 0; j < nc; ++j) w2[j] += t * wm[j];
+                    }
+                }
+                // C -= Vb W2
+                for (int64_t r = r0; r < p; ++r) {
+                    T *cr = C.row(r) + j0;
+                    const T *vr = &rb.V[(size_t)(r - r0) * cnt];
+                    for (int64_t l = 0; l < cnt; ++l) {
+                        const T f = vr[l];
+                        const T *w2 = &W2[(size_t)l * nc];
+                        for (int64_t j = 0; j < nc; ++j) cr[j] -= f * w2[j];
+                    }
                 }
             }
         }
