@@ -203,8 +203,18 @@ def main():
     ev[1].record(stream)
     torch.cuda.synchronize()
     copy_gbs = 2 * B1.numel() * B1.element_size() * 10 / (ev[0].elapsed_time(ev[1]) * 1e-3) / 1e9
+    # K1's dense access mix without the gather: read three blocks, write one in place
+    # (torch's elementwise addcmul_: B2 <- B2 + B0 * B1)
+    for _ in range(2):
+        B2.addcmul_(B0, B1)
+    ev[0].record(stream)
+    for _ in range(10):
+        B2.addcmul_(B0, B1)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    stream3_gbs = 4 * B1.numel() * B1.element_size() * 10 / (ev[0].elapsed_time(ev[1]) * 1e-3) / 1e9
     log(f"phases: orthonormalize {orth_ms:.2f} ms, Rayleigh-Ritz {rr_ms:.2f} ms, residuals {res_ms:.2f} ms; "
-        f"device copy {copy_gbs:.0f} GB/s")
+        f"device copy {copy_gbs:.0f} GB/s; 3-read/1-write pass {stream3_gbs:.0f} GB/s")
 
     traffic = None
     tpath = os.path.join(ROOT, "profiles", f"traffic_{cfg.name}_{args.form}.json")
@@ -240,7 +250,9 @@ def main():
         "phase_ms": {"filter": round(filt_med, 3), "orthonormalize": round(orth_ms, 3),
                      "rayleigh_ritz": round(rr_ms, 3), "residuals": round(res_ms, 3)},
         "measured_copy_gbs": round(copy_gbs, 1),
+        "measured_3r1w_gbs": round(stream3_gbs, 1),
         "dominant_frac_of_copy": round(achieved / copy_gbs, 4),
+        "dominant_frac_of_3r1w": round(achieved / stream3_gbs, 4),
         "roofline": {
             "kernel": "clenshaw_step_kernel<HAS_V=1,HAS_X=1> (gather src, read V in place, read X, write V)",
             "launches": len(steady_ms),
