@@ -208,8 +208,9 @@ int afsi_orthonormalize(const afsi_block *locked, afsi_block *X, afsi_block *wor
 
 /*
  * Rayleigh-Ritz (Algorithm 1): B = Q^H A Q, B = U diag(ritz) U^H (host, FP64),
- * V = Q U and AV = (A Q) U.  Q is n x p orthonormal and left unchanged; V and AV
- * are n x p; ritz_out[p] (host) ascending.  R64 or C128.  Synchronises `stream`.
+ * V = Q U and AV = A V (a sparse product, cheaper than forming (A Q) U).  Q is
+ * n x p orthonormal and left unchanged; V and AV are n x p; ritz_out[p] (host)
+ * ascending.  R64 or C128.  Synchronises `stream`.
  */
 int afsi_rayleigh_ritz(afsi_matrix_t A, const afsi_block *Q, afsi_block *V, afsi_block *AV,
                        double *ritz_out, void *stream);

@@ -19,5 +19,6 @@ dense         orthonormalisation, Rayleigh-Ritz, residual norms
 degree        initial degree rule and adaptive degree selection
 solver        the full adaptive filtered subspace iteration with locking
 closed_form   grid-Laplacian spectra (definition-level results)
+spectra       eigenvalues of a banded real symmetric matrix inside an interval
 bounds        Lanczos estimate of the spectral interval
 """

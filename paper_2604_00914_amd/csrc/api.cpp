@@ -312,8 +312,8 @@ void rayleigh_ritz_dev(afsi_matrix_t A, int dtype, const void *Q, void *V, void 
     AFSI_HIP(hipStreamSynchronize(s));
     host_eigh_or_throw(p, cplx, Bh, p, ritz, Uh, p);
     AFSI_HIP(hipMemcpyAsync(B, Uh, mbytes, hipMemcpyHostToDevice, s));
-    gemm_dev(dtype, V, ld, B, p, n, p, p, 1.0, 0.0, AV, ld, s);  // AV <- (A Q) U
     gemm_dev(dtype, Q, ld, B, p, n, p, p, 1.0, 0.0, V, ld, s);   // V  <- Q U
+    spmm_apply(A, dtype, V, AV, p, ld, s);                        // AV <- A V
     AFSI_HIP(hipStreamSynchronize(s));
 }
 

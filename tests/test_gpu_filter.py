@@ -172,13 +172,22 @@ def test_repeatable_bitwise():
     assert np.array_equal(y1, y2)
 
 
-def test_batched_groups_bitwise_equal_to_single_filters():
+BATCH_LAYOUTS = {
+    # narrow: 52 vectors per row (2 per lane), groups cover every column
+    "narrow": (104, [(0, 32, 7, (3.0, 3.5), 0), (32, 64, 12, (5.0, 5.3), 2), (96, 8, 5, (9.0, 11.0), 4)]),
+    # wide: 300 vectors per row (4 per lane, ragged second chunk), columns 200..209 and
+    # 546..599 in no group
+    "wide": (600, [(0, 200, 7, (3.0, 3.5), 0), (210, 328, 12, (5.0, 5.3), 2), (538, 8, 5, (9.0, 11.0), 4)]),
+}
+
+
+@pytest.mark.parametrize("layout", sorted(BATCH_LAYOUTS))
+def test_batched_groups_bitwise_equal_to_single_filters(layout):
     t = torch()
     A = laplacian_3d_dirichlet(10, 2.0, seed=4)
     lmin, lmax = 0.0, 14.0
     l1, l2 = co.affine_map(lmin, lmax)
-    groups = [(0, 32, 7, (3.0, 3.5), 0), (32, 64, 12, (5.0, 5.3), 2), (96, 8, 5, (9.0, 11.0), 4)]
-    ptot = 104
+    ptot, groups = BATCH_LAYOUTS[layout]
     X0 = start_block(A.n, ptot, seed=5)
     M = afsi.Matrix(A, bounds=(lmin, lmax))
     X = to_dev(X0)
@@ -203,6 +212,12 @@ def test_batched_groups_bitwise_equal_to_single_filters():
         assert np.array_equal(Yb, Ys.cpu().numpy()), g
         ref = oracle_filter(A, X0[:, c0:c0 + nc], lmin, lmax, iv[0], iv[1], k)
         _check(Yb, ref, F64_TOL)
+    # columns outside every group are never written
+    covered = np.zeros(ptot, bool)
+    for (c0, nc, k, iv, st) in groups:
+        covered[c0:c0 + nc] = True
+    for P in (P0, P1):
+        assert not P.cpu().numpy()[:, ~covered].any()
     M.close()
 
 

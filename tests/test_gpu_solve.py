@@ -115,6 +115,24 @@ def test_adaptive_lanczos_mode():
     _check_pairs(A, lam, V, ref, normA, 1e-10, 1e-9)
 
 
+@pytest.mark.parametrize("mixed", [False, True])
+def test_lap3d27_paper_mode_matches_banded_reference(mixed):
+    """The degree-consistent 27^3 reduction of the 100^3 workload (p = 360, kmax 120),
+    solved in the paper's adaptive mode (Lanczos damping m = 0.5, Algorithm 3 degree):
+    all 196 window eigenvalues of the banded-eigensolver fixture, exact count."""
+    from tests.golden_util import lap3d27_window
+
+    A, (lmin, lmax), (a, b), cfg = build_config("lap3d_pot_27")
+    ref = lap3d27_window()
+    normA = max(abs(lmin), abs(lmax))
+    st, lam, res, r, V = gpu_solve(A, a, b, lmin, lmax, start_block(A.n, cfg.p, 0), cfg.degree,
+                                   mixed=mixed, adaptive=True, damping="lanczos", max_iter=600)
+    assert st == 0 and r.converged and r.count == ref.size == 196
+    tol = (1e-5, 1e-5) if mixed else (1e-10, 1e-9)
+    _check_pairs(A, lam, V, ref, normA, *tol)
+    assert r.avg_degree <= cfg.degree
+
+
 def test_iteration_limit_returns_partial():
     A, (lmin, lmax), (a, b), cfg = build_config("lap2d_64")
     st, lam, res, r, V = gpu_solve(A, a, b, lmin, lmax, start_block(A.n, 64, 0), 60, max_iter=2)

@@ -12,6 +12,11 @@ Sizes follow the five workloads the build is measured on:
    p = 640, degree 200, Jackson, FP32 filter with FP64 projections.
 5. Serving stream (see :mod:`workloads.stream`).
 
+plus a degree-consistent reduction of workload 2 that converges at its degree:
+27^3 grid (n = 19683), the same recipe, a mid-spectrum window sized for ~200
+eigenvalues at the measured density of states (0.1435 per site per unit energy),
+p = 360 (1.8 x 200), degree 120, Jackson.
+
 Spectral bounds are the closed form for config 1 and Gershgorin discs otherwise.
 ``scale`` shrinks a workload for tests (grid edge or n); the recipe stays the same.
 """
@@ -86,6 +91,18 @@ CONFIGS = {
         complex_=False,
         filter_dtypes=("f64", "f32"),
         interval=_centred(1.39e-3),
+    ),
+    "lap3d_pot_27": WorkloadConfig(
+        name="lap3d_pot_27",
+        description="3D 7-point Dirichlet Laplacian 27^3 + 2*U(0,1) potential, n=19683, ~200-eigenvalue window",
+        make_matrix=lambda size, seed: laplacian_3d_dirichlet(size, potential_scale=2.0, seed=seed),
+        size=27,
+        p=360,
+        degree=120,
+        damping="jackson",
+        complex_=False,
+        filter_dtypes=("f64", "f32"),
+        interval=_centred(200.0 / (0.1435 * 27 ** 3)),
     ),
     "tb3d_64": WorkloadConfig(
         name="tb3d_64",
