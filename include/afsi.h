@@ -45,7 +45,8 @@ typedef enum {
     AFSI_E_HIP = -3,       /* a HIP runtime call failed */
     AFSI_E_NOT_HPD = -4,   /* Gram matrix not positive definite even after the shift */
     AFSI_E_BOUNDS = -5,    /* filter output grew: spectral bounds do not enclose A */
-    AFSI_E_NOCONV = -6,    /* iteration limit reached; partial results returned */
+    AFSI_E_NOCONV = -6,    /* iteration limit reached (partial results returned), or the
+                              host eigensolver's QR iteration did not converge */
     AFSI_E_BUSY = -7,      /* serving: request does not fit the device budget now */
     AFSI_E_NODEVICE = -8   /* no usable gfx950 device */
 } afsi_status;
@@ -259,7 +260,10 @@ int afsi_lock_select(const double *ritz, int64_t p, const double *res, uint8_t *
  * Host Hermitian eigensolver used by Rayleigh-Ritz (Algorithm 1): B (p x p,
  * row-major, ldb; R64 or C128, only its Hermitian part is used) = U diag(w) U^H,
  * w[p] ascending, U (p x p, ldu, same dtype) unitary.  Householder tridiagonal
- * reduction + implicit-shift symmetric QR.  Pure host function.
+ * reduction + implicit-shift symmetric QR.  Pure host function.  AFSI_E_INVALID
+ * if B has a non-finite entry; AFSI_E_NOCONV if the QR iteration does not converge
+ * (also returned by afsi_rayleigh_ritz and afsi_solve; afsi_solve then reports no
+ * locked pairs).
  */
 int afsi_host_eigh(int64_t p, int32_t dtype, const double *B, int64_t ldb, double *w, double *U,
                    int64_t ldu);
@@ -348,13 +352,19 @@ typedef struct {
 int afsi_server_create(int device, int64_t hbm_budget_bytes, afsi_server_t *out);
 /* Stops the pool threads (running requests fail), frees everything. */
 int afsi_server_destroy(afsi_server_t S);
-/* Reserve `cols` columns for A's pools (slices of one matrix share them). */
+/*
+ * Reserve `cols` columns for A's pools (slices of one matrix share them).  A pool is
+ * created with max(cols, the first request's width) columns and lives while it has
+ * requests; a request wider than a live pool of its matrix and filter precision
+ * waits until that pool has drained, so size the pool for the widest request.
+ */
 int afsi_server_set_pool_columns(afsi_server_t S, afsi_matrix_t A, int64_t cols);
 /*
  * Queue a solve of [a, b] on A (bounds set) with block width p and `opts`
  * (opts->filter_dtype picks the plain or mixed form).  The start block is N(0,1)
  * from a counter-based generator keyed by `seed`.  AFSI_E_BUSY if the request
- * cannot fit the budget even alone.  Returns at once.
+ * cannot fit the budget even alone.  Returns at once.  A request whose device
+ * allocation fails at admission finishes with status AFSI_E_NOMEM.
  */
 int afsi_server_submit(afsi_server_t S, afsi_matrix_t A, double a, double b, int64_t p,
                        const afsi_options *opts, uint64_t seed, int64_t *id);

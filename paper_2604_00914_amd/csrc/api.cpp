@@ -44,13 +44,14 @@ DeviceGuard::~DeviceGuard() {
 void *Workspace::dev_reserve(int slot, size_t bytes) {
     if (bytes == 0) bytes = 256;
     if (bytes > dev_bytes[slot]) {
+        // grow by at least half, so that slowly increasing requests reallocate rarely
+        const size_t want = std::max(bytes, dev_bytes[slot] + dev_bytes[slot] / 2);
         if (dev[slot]) {
             AFSI_HIP(hipStreamSynchronize(stream));
             AFSI_HIP(hipFree(dev[slot]));
             dev[slot] = nullptr;
             dev_bytes[slot] = 0;
         }
-        const size_t want = std::max(bytes, dev_bytes[slot] + dev_bytes[slot] / 2);
         AFSI_HIP(hipMalloc(&dev[slot], want));
         dev_bytes[slot] = want;
     }
@@ -664,8 +665,6 @@ int afsi_block_inner(const afsi_block *X, const afsi_block *Y, afsi_block *G, vo
         AFSI_REQUIRE(X->rows == Y->rows && G->rows == X->cols && G->cols == Y->cols,
                      "shapes do not match G = X^H Y");
         AFSI_REQUIRE(!overlap(G, X) && !overlap(G, Y), "G overlaps an input");
-        const int comp = X->dtype == AFSI_C128 ? 2 : 1;
-        (void)comp;
         inner_dev(X->dtype, X->ptr, X->ld, Y->ptr, Y->ld, X->rows, X->cols, Y->cols,
                   (double *)G->ptr, G->ld, as_stream(stream));
     });
@@ -798,8 +797,14 @@ int afsi_host_eigh(int64_t p, int32_t dtype, const double *B, int64_t ldb, doubl
 namespace afsi {
 void host_eigh_or_throw(int64_t p, bool cplx, const double *B, int64_t ldb, double *w, double *U,
                         int64_t ldu) {
+    const int comp = cplx ? 2 : 1;
+    for (int64_t i = 0; i < p; ++i)
+        for (int64_t j = 0; j < comp * p; ++j)
+            AFSI_REQUIRE(std::isfinite(B[i * comp * ldb + j]),
+                         "Hermitian eigensolver input has a non-finite entry at row %lld",
+                         (long long)i);
     if (!host_eigh(p, cplx, B, ldb, w, U, ldu))
-        AFSI_FAIL(AFSI_E_HIP, "Hermitian eigensolver (tridiagonal QR) did not converge");
+        AFSI_FAIL(AFSI_E_NOCONV, "Hermitian eigensolver (tridiagonal QR) did not converge");
 }
 }  // namespace afsi
 

@@ -220,21 +220,22 @@ __global__ __launch_bounds__(256, 4) void clenshaw_batched_kernel(
     const int row = __builtin_amdgcn_readfirstlane((int)(item % n));
     const int c0 = __builtin_amdgcn_readfirstlane((int)(item / n)) * 64 * VN;
     const int start = rp[row], end = rp[row + 1];
-    // per vector: its group, its source block and a load index that is always inside
-    // the block (vectors past p16 or outside every group are computed and discarded),
-    // so the gather loop has no lane-dependent branches
+    // per vector: its group, its source block and a load index that is always a whole
+    // vector inside the block (a vector outside every group is read at the first
+    // vector of group 0 and its product discarded), so the gather loop has no
+    // lane-dependent branches
     int grp[VN], vix[VN];
     const vec *sp[VN];
     int live = 0;
 #pragma unroll
     for (int v = 0; v < VN; ++v) {
         const int vi = c0 + v * 64 + lane;
-        vix[v] = vi < p16 ? vi : p16 - 1;
         grp[v] = -1;
         for (int g = 0; g < args.ngroups; ++g)
             if (vi >= args.vec0[g] && vi < args.vec1[g]) grp[v] = g;
         const int s = grp[v] >= 0 ? args.src[grp[v]] : 0;
         sp[v] = s == 0 ? X : (s == 1 ? P0 : P1);
+        vix[v] = grp[v] >= 0 ? vi : args.vec0[0];
         live |= (grp[v] >= 0) << v;
     }
     if (__ballot(live != 0) == 0) return;  // no lane of this wave has a live vector

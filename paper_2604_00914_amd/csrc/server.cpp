@@ -133,6 +133,17 @@ int64_t find_run(const std::vector<uint8_t> &used, int64_t need, int64_t E) {
 
 void pool_thread(Pool *P);
 
+// A queued request that cannot be started (caller holds S->mu; the caller removes
+// it from the queue).
+void fail_queued(Server *S, Request *r, int status, const char *msg) {
+    r->state = Q_FAILED;
+    r->status = status;
+    r->error = msg;
+    r->t_done = S->now();
+    S->finished.push_back(r->id);
+    ++S->n_done;
+}
+
 // Admit every queued request that fits (caller holds S->mu).
 void try_admit(Server *S) {
     for (auto it = S->queue.begin(); it != S->queue.end();) {
@@ -181,7 +192,8 @@ void try_admit(Server *S) {
             } catch (...) {
                 for (auto b : np->B) (void)hipFree(b);
                 for (auto b : np->F) (void)hipFree(b);
-                ++it;
+                fail_queued(S, r, AFSI_E_NOMEM, "device allocation of the request's pool failed");
+                it = S->queue.erase(it);
                 continue;
             }
             np->bytes = new_pool;
@@ -200,7 +212,9 @@ void try_admit(Server *S) {
             DeviceGuard dg(S->device);
             AFSI_HIP(hipMalloc(&r->evecs, std::max<size_t>(r->evec_bytes, 16)));
         } catch (...) {
-            ++it;
+            r->evecs = nullptr;
+            fail_queued(S, r, AFSI_E_NOMEM, "device allocation of the eigenvector block failed");
+            it = S->queue.erase(it);
             continue;
         }
         S->in_use += (int64_t)r->evec_bytes;
@@ -278,6 +292,15 @@ void start_filter(Pool *P, Session &s) {
 
 enum { DP_CONTINUE = 0, DP_CONVERGED = 1, DP_LIMIT = 2 };
 
+// Progress counters that afsi_server_info reads while the request runs: updated
+// under the server lock (the pool thread is their only writer).
+void publish(Pool *P, Request *r, int iterations, int64_t spmv, int64_t locked) {
+    std::lock_guard<std::mutex> lk(P->S->mu);
+    r->iterations += iterations;
+    r->spmv += spmv;
+    r->n_lock += locked;
+}
+
 // One pass of the dense steps after a filter; says whether the request goes on.
 int dense_phase(Pool *P, Session &s) {
     Request *r = s.r;
@@ -296,9 +319,8 @@ int dense_phase(Pool *P, Session &s) {
         w = col_ptr(P->B[3 - outi], s.col0, dt);
     }
     void *v = col_ptr(P->B[0], s.col0, dt);
-    r->spmv += (int64_t)s.k_cur * pa;
     s.degrees.push_back(s.k_cur);
-    ++r->iterations;
+    publish(P, r, 1, (int64_t)s.k_cur * pa, 0);
     if (r->n_lock > 0) project_out_dev(dt, r->evecs, r->p, r->n_lock, q, ld, n, pa, P->stream);
     double maxn2 = 0.0;
     orthonormalize_dev(dt, q, w, n, pa, ld, P->stream, &maxn2);
@@ -307,7 +329,7 @@ int dense_phase(Pool *P, Session &s) {
                   std::sqrt(maxn2));
     std::vector<double> ritz(pa), res(pa);
     rayleigh_ritz_dev(r->A, dt, q, v, w, n, pa, ld, ritz.data(), P->stream);
-    r->spmv += pa;
+    publish(P, r, 0, pa, 0);
     std::vector<uint8_t> I(pa), lock(pa);
     int64_t e = 0;
     for (int64_t j = 0; j < pa; ++j) {
@@ -338,7 +360,7 @@ int dense_phase(Pool *P, Session &s) {
                 AFSI_HIP(hipMemcpy2DAsync(v, ld * eb, w, ld * eb, keep.size() * eb, n,
                                           hipMemcpyDeviceToDevice, P->stream));
             }
-            r->n_lock += (int64_t)lk.size();
+            publish(P, r, 0, 0, (int64_t)lk.size());
             s.p_act -= (int64_t)lk.size();
         }
         if (done) return DP_CONVERGED;
@@ -416,6 +438,9 @@ void pool_thread(Pool *P) {
                 it->r->error = afsi_last_error();
                 finish(P, *it, e.status, it->r->error);
                 done.push_back(it);
+            } catch (const std::exception &e) {
+                finish(P, *it, AFSI_E_NOMEM, e.what());
+                done.push_back(it);
             }
         }
         for (auto it : done) P->sessions.erase(it);
@@ -447,6 +472,10 @@ void pool_thread(Pool *P) {
             for (auto *s : filt) s->phase = -1, finish(P, *s, e.status, msg);
             P->sessions.remove_if([](const Session &s) { return s.phase == -1; });
             continue;
+        } catch (const std::exception &e) {
+            for (auto *s : filt) s->phase = -1, finish(P, *s, AFSI_E_NOMEM, e.what());
+            P->sessions.remove_if([](const Session &s) { return s.phase == -1; });
+            continue;
         }
         for (auto *s : filt)
             if (++s->step == s->k_cur) s->phase = PH_DENSE;
@@ -461,6 +490,9 @@ void pool_thread(Pool *P) {
                 }
             } catch (const Error &e) {
                 finish(P, *it, e.status, afsi_last_error());
+                done.push_back(it);
+            } catch (const std::exception &e) {
+                finish(P, *it, AFSI_E_NOMEM, e.what());
                 done.push_back(it);
             }
         }

@@ -155,6 +155,20 @@ def test_host_eigh_degenerate_and_diagonal(cplx):
 
 
 @pytest.mark.parametrize("cplx", [False, True])
+def test_host_eigh_rejects_non_finite_input(cplx):
+    B = np.eye(6, dtype=np.complex128 if cplx else np.float64)
+    B[4, 1] = np.nan
+    with pytest.raises(afsi.AfsiError) as e:
+        afsi.afsi_host_eigh(B)
+    assert e.value.status == -1 and "non-finite" in str(e.value)
+    if cplx:
+        B = np.eye(6, dtype=np.complex128)
+        B[2, 3] = complex(0.0, np.inf)
+        with pytest.raises(afsi.AfsiError):
+            afsi.afsi_host_eigh(B)
+
+
+@pytest.mark.parametrize("cplx", [False, True])
 def test_host_cholesky_inverse(cplx):
     rng = np.random.default_rng(5)
     X = rng.standard_normal((300, 30)) * np.logspace(0, -6, 30)
