@@ -82,10 +82,16 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run three plain device copies of one block (counter calibration)")
+    ap.add_argument("--cpu-baseline-sweep", default=None, metavar="OUT",
+                    help="only time the oracle (host cores, all threads and one) on every "
+                         "workload plus full converging solves; one JSON line per case into OUT")
     ap.add_argument("--sweep", default=None, metavar="OUT",
                     help="only measure the filter alone on every workload and precision; "
                          "one JSON line per case into OUT")
     args = ap.parse_args()
+    if args.cpu_baseline_sweep:
+        cpu_sweep(args.cpu_baseline_sweep)   # host only: the oracle on every workload
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
               "(see the sharding notes in DESIGN.md); use --gpus 1", file=sys.stderr)
@@ -533,6 +539,84 @@ def serve_rates(afsi, M_slices, num):
     return out
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_sweep(path, budget_s=10.0):
+    """The oracle on the host cores: per workload a bounded sample of FP64 Clenshaw
+    products with all threads and with one thread (one-thread samples on a column
+    subset for the wide workloads, scaled to full width), extrapolated to one full
+    filter; plus full oracle solves of the converging lap2d_64 workload."""
+    from oracle import coefficients as co
+    from oracle import native
+    from oracle import solver as osolver
+    from oracle.filter import clenshaw_steps
+    from workloads import build_config, start_block
+
+    native.build(force=False)
+    all_threads = native.num_threads()
+    out = open(path, "w")
+
+    def sample(A, X0, c, l1, l2, k, secs):
+        gen = clenshaw_steps(A, X0, c, l1, l2)
+        t0 = time.perf_counter()
+        next(gen)
+        one = time.perf_counter() - t0
+        steps = max(1, min(k - 1, int(secs / max(one, 1e-4))))
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            next(gen)
+        return steps, (time.perf_counter() - t0) / steps
+
+    for name in ("lap2d_64", "lap3d_pot_100", "tb3d_64", "rand_2m"):
+        A, (lmin, lmax), (a, b), cfg = build_config(name, seed=0)
+        n, p, k = A.n, cfg.p, cfg.degree
+        cplx = A.is_complex
+        s = 16 if cplx else 8
+        c = co.filter_coefficients(lmin, lmax, a, b, k, cfg.damping)
+        l1, l2 = co.affine_map(lmin, lmax)
+        rec = {"workload": name, "n": n, "nnz": A.nnz, "p": p, "degree": k, "dtype": "c128" if cplx else "f64",
+               "cpu": cpu_model(), "threads": all_threads}
+        step_bytes = A.nnz * (s + 4) + 4 * (n + 1) + 4 * n * p * s
+        for label, threads, cols in (("all_threads", all_threads, p), ("one_thread", 1, min(p, 64 if n > 1e5 else p))):
+            native.set_num_threads(threads)
+            X0 = start_block(n, cols, seed=1, complex_=cplx)
+            steps, per = sample(A, X0, c, l1, l2, k, budget_s)
+            del X0
+            scale = p / cols
+            per_full = per * scale
+            rec[label] = {"threads": threads, "sample_products": steps, "sample_cols": cols,
+                          "s_per_product": round(per_full, 4), "filter_s_extrapolated": round(per_full * k, 2),
+                          "gbs": round(step_bytes / per_full / 1e9, 3)}
+            log(f"cpu oracle {name} {label}: {rec[label]}")
+        native.set_num_threads(all_threads)
+        out.write(json.dumps(rec) + "\n")
+        out.flush()
+    # full oracle solves where they converge
+    A, (lmin, lmax), (a, b), cfg = build_config("lap2d_64")
+    for threads in (all_threads, 1):
+        native.set_num_threads(threads)
+        X0 = start_block(A.n, cfg.p, seed=0)
+        o = osolver.Options(kmax=cfg.degree)
+        t0 = time.perf_counter()
+        res = osolver.solve(A, a, b, lmin, lmax, X0, o)
+        dt = time.perf_counter() - t0
+        rec = {"workload": "lap2d_64 solve", "threads": threads, "seconds": round(dt, 3),
+               "eigenpairs": int(len(res.eigenvalues)), "iterations": int(res.iterations),
+               "eigenpairs_per_s": round(len(res.eigenvalues) / dt, 2), "cpu": cpu_model()}
+        log(f"cpu oracle solve: {rec}")
+        out.write(json.dumps(rec) + "\n")
+    native.set_num_threads(all_threads)
+    out.close()
+
+
 def cpu_baseline(A, p, k, lmin, lmax, a, b, cfg, sx, sample_steps):
     """The oracle's Clenshaw filter on the same matrix, a few products, on the host cores."""
     from oracle import coefficients as co
@@ -555,7 +639,22 @@ def cpu_baseline(A, p, k, lmin, lmax, a, b, cfg, sx, sample_steps):
     for _ in range(steps):
         next(gen)
     dt = time.perf_counter() - t0
+    del gen, X0
     step_bytes = A.nnz * (8 + 4) + 4 * (A.n + 1) + 4 * A.n * p * 8
+    # one thread, on a 64-column sample of the block (bytes scaled to the full width)
+    cols = min(p, 64)
+    native.set_num_threads(1)
+    try:
+        X1 = start_block(A.n, cols, seed=1)
+        gen = clenshaw_steps(A, X1, c, l1, l2)
+        next(gen)
+        t1 = time.perf_counter()
+        n1 = 2
+        for _ in range(n1):
+            next(gen)
+        per1 = (time.perf_counter() - t1) / n1 * (p / cols)
+    finally:
+        native.set_num_threads(threads)
     return {
         "value": round(steps * step_bytes / dt / 1e9, 3),
         "unit": "GB/s",
@@ -564,6 +663,10 @@ def cpu_baseline(A, p, k, lmin, lmax, a, b, cfg, sx, sample_steps):
         "sample": f"{steps} Clenshaw products (of {k}) of the FP64 oracle on the full "
                   f"{cfg.name} matrix, n={A.n}, p={p}; {dt:.1f} s",
         "seconds_per_product": round(dt / steps, 4),
+        "cpu": cpu_model(),
+        "one_thread": {"value": round(step_bytes / per1 / 1e9, 3), "unit": "GB/s",
+                       "seconds_per_product": round(per1, 3),
+                       "sample": f"{n1} products on a {cols}-column block, scaled to p={p}"},
     }
 
 

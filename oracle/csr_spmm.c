@@ -58,3 +58,14 @@ int oracle_num_threads(void)
     }
     return nt;
 }
+
+/* Thread count of the products above (measurement only: single-thread baselines). */
+void oracle_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    omp_set_num_threads(n > 0 ? n : 1);
+#else
+    (void)n;
+#endif
+}

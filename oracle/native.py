@@ -44,12 +44,19 @@ def lib():
                 ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
             ]
         L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_set_num_threads.restype = None
+        L.oracle_set_num_threads.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
 
 
 def num_threads() -> int:
     return int(lib().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Thread count of later products (for single-thread timing)."""
+    lib().oracle_set_num_threads(int(n))
 
 
 def spmm(A, B: np.ndarray) -> np.ndarray:

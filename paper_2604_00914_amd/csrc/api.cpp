@@ -12,7 +12,6 @@
 #include <utility>
 #include <vector>
 
-#include "clenshaw_kernels.h"
 #include "internal.h"
 
 namespace afsi {

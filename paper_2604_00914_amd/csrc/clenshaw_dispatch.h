@@ -81,27 +81,6 @@ void dispatch_step(const MatView &A, const void *src, const void *X, void *dst, 
     }
 }
 
-template <class Tr, int VN>
-void launch_batched(const MatView &A, const void *X, void *P0, void *P1, int p16, int64_t ldv,
-                    const BatchArgs &args, hipStream_t s) {
-    using vec = typename Tr::vec;
-    const int nchunks = (p16 + 64 * VN - 1) / (64 * VN);
-    const int64_t items = A.n * (int64_t)nchunks;
-    AFSI_REQUIRE(items < (1LL << 31), "batched step: rows x column chunks too large");
-    const Grid g = xcd_grid(items, 4);  // 4 items (waves) per workgroup
-    hipLaunchKernelGGL((clenshaw_batched_kernel<Tr, VN, 8>), dim3((unsigned)g.grid), dim3(256), 0, s,
-                       (int)A.n, A.rp, A.ci, (const typename Tr::val *)A.val, (const vec *)X,
-                       (vec *)P0, (vec *)P1, ldv, p16, nchunks, g.group, g.nblocks, args);
-}
-
-// 2 vectors per lane (2 KB chunks of an FP64 row): on 16 slices x 96 columns of the
-// 100^3 matrix, 14.8 ms per step against 18.0 ms with 4 vectors per lane
-template <class Tr>
-void dispatch_batched(const MatView &A, const void *X, void *P0, void *P1, int p16, int64_t ldv,
-                      const BatchArgs &args, hipStream_t s) {
-    launch_batched<Tr, 2>(A, X, P0, P1, p16, ldv, args, s);
-}
-
 template <class Sr>
 void dispatch_scalar(const MatView &A, const void *src, const void *X, void *dst, int p,
                      int64_t ld, bool hv, bool hx, double sg, double ta, double al, hipStream_t s) {
@@ -122,10 +101,6 @@ void dispatch_scalar(const MatView &A, const void *src, const void *X, void *dst
                      int64_t ldv, bool hv, bool hx, double sg, double ta, double al,               \
                      hipStream_t s) {                                                               \
         dispatch_step<TR>(A, src, X, dst, p16, ldv, hv, hx, sg, ta, al, s);                         \
-    }                                                                                               \
-    void NAME##_batched(const MatView &A, const void *X, void *P0, void *P1, int p16, int64_t ldv,  \
-                        const BatchArgs &args, hipStream_t s) {                                     \
-        dispatch_batched<TR>(A, X, P0, P1, p16, ldv, args, s);                                      \
     }                                                                                               \
     void NAME##_scalar(const MatView &A, const void *src, const void *X, void *dst, int p,          \
                        int64_t ld, bool hv, bool hx, double sg, double ta, double al,              \

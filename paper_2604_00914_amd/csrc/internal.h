@@ -133,7 +133,16 @@ Workspace &workspace(hipStream_t stream);
 
 // ---------------------------------------------------------------- kernels (clenshaw_*.hip)
 
-struct BatchArgs;
+// Batched step arguments: column groups with their own source block, flags and
+// scalars (group g owns 16-byte row vectors [vec0, vec1)).
+struct BatchArgs {
+    int ngroups;
+    int vec0[64], vec1[64];   // group g owns row vectors [vec0, vec1)
+    int src[64], dst[64];     // 0 = X, 1 = P0, 2 = P1
+    int has_v[64];
+    double sigma[64], tau[64], alpha[64];
+};
+
 #define AFSI_DECLARE_STEP_ENTRY(NAME)                                                               \
     void NAME##_step(const MatView &A, const void *src, const void *X, void *dst, int p16,          \
                      int64_t ldv, bool hv, bool hx, double sg, double ta, double al,               \
