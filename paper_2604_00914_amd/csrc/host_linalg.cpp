@@ -303,64 +303,89 @@ static bool eigh_impl(int64_t p, const T *B, int64_t ldb, double *w, T *U, int64
             A[j * p + i] = conjv(h);
         }
     }
-    // Householder reduction; reflector k acts on indices k+1..p-1 with unit vector V[k].
-    // The reflector is formed by one thread; the symmetric product u = A_sub conj(v)...
-    // (u_i = sum_j A_ij v_j), and the rank-2 update A_sub -= v w^H + w v^H with
-    // w = 2u - 2 (v^H u) v, are shared by rows.
+    // Householder reduction with look-ahead.  Reflector k (unit v_k on indices
+    // k+1..p-1, H_k = I - 2 v_k v_k^H) maps column k to (.., alpha_k, 0, ..).  With
+    // u_k = A_k v_k (A_k the trailing matrix from k+1), gamma = v_k^H u_k and
+    // w_k = 2 u_k - 2 gamma v_k, H_k A_k H_k = A_k - v_k w_k^H - w_k v_k^H.  Per column,
+    // one thread applies that update to column k+1 only and forms reflector k+1 from
+    // it; then the threads sweep the rows once, each row receiving update k and giving
+    // its entry of u_{k+1} = A_{k+1} v_{k+1}: two barriers per column and one pass over
+    // the trailing matrix.  Row k+1 is never read again and is left stale.
     std::vector<std::vector<T>> V(p);
-    std::vector<T> u(p), wv(p), v(p);
-    bool skip = false;
-    T alpha = T(0);
+    std::vector<T> vb[2] = {std::vector<T>(p), std::vector<T>(p)};
+    std::vector<T> ub[2] = {std::vector<T>(p), std::vector<T>(p)};
+    std::vector<T> wk(p), wkc(p);  // w_k and its conjugate
+    bool have[2] = {false, false};
+    // reflector from column k (rows k+1.., up to date); false if the column is reduced
+    auto make_reflector = [&](int64_t k, std::vector<T> &v, T &alpha) -> bool {
+        const int64_t m = p - k - 1;
+        double xn2 = 0.0;
+        for (int64_t i = 0; i < m; ++i) xn2 += absq(A[(k + 1 + i) * p + k]);
+        const double xn = std::sqrt(xn2);
+        const T x0 = A[(k + 1) * p + k];
+        alpha = x0;
+        if (xn == 0.0) return false;
+        const double ax0 = std::sqrt(absq(x0));
+        const T phase = ax0 > 0 ? x0 / ax0 : T(1);
+        alpha = -phase * xn;
+        for (int64_t i = 0; i < m; ++i) v[i] = A[(k + 1 + i) * p + k];
+        v[0] -= alpha;
+        double vn2 = 0.0;
+        for (int64_t i = 0; i < m; ++i) vn2 += absq(v[i]);
+        const double inv = 1.0 / std::sqrt(vn2);
+        for (int64_t i = 0; i < m; ++i) v[i] *= inv;
+        return true;
+    };
+    std::vector<T> alphas(p, T(0));
     const bool householder_threads =
         p * (int64_t)(sizeof(T) / sizeof(double)) >= kHouseholderParallelMin;
+    if (p > 2) {
+        have[0] = make_reflector(0, vb[0], alphas[0]);
 #pragma omp parallel if (householder_threads)
-    for (int64_t k = 0; k + 2 < p; ++k) {
-        const int64_t m = p - k - 1;
-#pragma omp single
         {
-            double xn2 = 0.0;
-            for (int64_t i = 0; i < m; ++i) xn2 += absq(A[(k + 1 + i) * p + k]);
-            const double xn = std::sqrt(xn2);
-            skip = xn == 0.0;
-            if (!skip) {
-                const T x0 = A[(k + 1) * p + k];
-                const double ax0 = std::sqrt(absq(x0));
-                const T phase = ax0 > 0 ? x0 / ax0 : T(1);
-                alpha = -phase * xn;
-                for (int64_t i = 0; i < m; ++i) v[i] = A[(k + 1 + i) * p + k];
-                v[0] -= alpha;
-                double vn2 = 0.0;
-                for (int64_t i = 0; i < m; ++i) vn2 += absq(v[i]);
-                const double vn = std::sqrt(vn2);
-                skip = vn == 0.0;
-                if (!skip)
-                    for (int64_t i = 0; i < m; ++i) v[i] /= vn;
+            if (have[0]) {
+#pragma omp for schedule(static)
+                for (int64_t i = 0; i < p - 1; ++i)
+                    ub[0][i] = dot_lanes(&A[(1 + i) * p + 1], vb[0].data(), p - 1);
             }
-        }
-        if (skip) continue;
-#pragma omp for schedule(static)
-        for (int64_t i = 0; i < m; ++i) u[i] = dot_lanes(&A[(k + 1 + i) * p + k + 1], v.data(), m);
+            for (int64_t k = 0; k + 2 < p; ++k) {
+                const int cur = (int)(k & 1), nxt = cur ^ 1;
+                const std::vector<T> &v = vb[cur];
 #pragma omp single
-        {
-            T gamma = T(0);
-            for (int64_t i = 0; i < m; ++i) gamma += conjv(v[i]) * u[i];
-            const double g = realv(gamma);
-            for (int64_t i = 0; i < m; ++i) wv[i] = 2.0 * u[i] - 2.0 * g * v[i];
-            // conjugated copies make the row update a pair of plain axpys
-            for (int64_t i = 0; i < m; ++i) u[i] = conjv(wv[i]);
-        }
+                {
+                    const int64_t m = p - k - 1;
+                    if (have[cur]) {
+                        const std::vector<T> &u = ub[cur];
+                        T gamma = T(0);
+                        for (int64_t i = 0; i < m; ++i) gamma += conjv(v[i]) * u[i];
+                        const double g = realv(gamma);
+                        for (int64_t i = 0; i < m; ++i) {
+                            wk[i] = 2.0 * u[i] - 2.0 * g * v[i];
+                            wkc[i] = conjv(wk[i]);
+                        }
+                        // update k on column k+1 (rows k+1.., index i = row - (k+1))
+                        const T w0c = wkc[0], v0c = conjv(v[0]);
+                        for (int64_t i = 0; i < m; ++i) A[(k + 1 + i) * p + k + 1] -= v[i] * w0c + wk[i] * v0c;
+                        V[k].assign(v.begin(), v.begin() + m);
+                    }
+                    A[(k + 1) * p + k] = alphas[k];
+                    have[nxt] = k + 3 < p && make_reflector(k + 1, vb[nxt], alphas[k + 1]);
+                }
+                // rows k+2..: update k on columns k+2.., then u_{k+1} entries
+                const bool upd = have[cur], nx = have[nxt];
+                const int64_t m1 = p - k - 2;  // length of v_{k+1}
 #pragma omp for schedule(static)
-        for (int64_t i = 0; i < m; ++i) {
-            T *ar = &A[(k + 1 + i) * p + k + 1];
-            const T vi = v[i], wi = wv[i];
-            for (int64_t j = 0; j < m; ++j) ar[j] -= vi * u[j] + wi * conjv(v[j]);
-        }
-#pragma omp single
-        {
-            A[(k + 1) * p + k] = alpha;
-            A[k * p + k + 1] = conjv(alpha);
-            for (int64_t i = 1; i < m; ++i) A[(k + 1 + i) * p + k] = A[k * p + k + 1 + i] = T(0);
-            V[k].assign(v.begin(), v.begin() + m);
+                for (int64_t r = k + 2; r < p; ++r) {
+                    T *ar = &A[r * p + k + 2];
+                    if (upd) {
+                        const T vi = v[r - k - 1], wi = wk[r - k - 1];
+                        const T *wcj = &wkc[1];
+                        const T *vj = &v[1];
+                        for (int64_t j = 0; j < m1; ++j) ar[j] -= vi * wcj[j] + wi * conjv(vj[j]);
+                    }
+                    if (nx) ub[nxt][r - k - 2] = dot_lanes(ar, vb[nxt].data(), m1);
+                }
+            }
         }
     }
     // real tridiagonal via phases delta_{k+1} = delta_k e_k / |e_k|

@@ -127,7 +127,7 @@ def test_lock_select_matches_oracle_sequences():
 
 
 @pytest.mark.parametrize("cplx", [False, True])
-@pytest.mark.parametrize("p", [1, 2, 5, 64, 200])
+@pytest.mark.parametrize("p", [1, 2, 3, 5, 64, 200, 333])
 def test_host_eigh_against_numpy(cplx, p):
     rng = np.random.default_rng(p)
     M = rng.standard_normal((p, p)) + (1j * rng.standard_normal((p, p)) if cplx else 0)
