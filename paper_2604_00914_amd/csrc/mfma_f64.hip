@@ -6,15 +6,17 @@
 //        waves own 32 x 64 sub-tiles (2 x 4 MFMA accumulators).  Rows are consumed
 //        16 at a time through double-buffered LDS tiles filled by coalesced loads.
 //        Each chunk's partial tile goes to scratch; a second kernel adds the chunks
-//        in chunk order (no atomics: bitwise reproducible for fixed n, p, q).
+//        in chunk order (no atomics: bitwise reproducible for fixed n, p, q).  The
+//        chunk count is a multiple of 8 sized so that each XCD runs its tiles in
+//        one resident round.
 // gemm : Y = alpha X M + beta Y for n x p X and small p x q M (X R^{-1}, Q U,
 //        (A Q) U, the locked-vector update).  Same 64 x 128 tiles over (rows of Y,
 //        columns of Y), the reduction over p runs through the same LDS pipeline with
 //        X stored transposed so operand reads are conflict-free.  Column tiles of a
 //        row tile are adjacent in the grid, so X rows are reused from cache.  For an
 //        upper-triangular M (R^{-1}) a column tile stops at its last column's row.
-// A Gram product with X == Y computes only tiles that reach the upper triangle and
-// mirrors the rest, so the Cholesky-QR Gram is exactly symmetric.
+// A Gram product with X == Y takes its lower triangle from the upper one in the
+// chunk reduction, so the Cholesky-QR Gram is exactly Hermitian.
 // Complex Hermitian blocks use real views: a complex n x p block with leading
 // dimension ld is a real n x 2p block with leading dimension 2 ld, and
 //   X^H Y = (Gr[2i,2j] + Gr[2i+1,2j+1]) + i (Gr[2i,2j+1] - Gr[2i+1,2j])  with Gr = Xr^T Yr,
@@ -66,7 +68,7 @@ __global__ __launch_bounds__(256) void gram_f64_kernel(const double *__restrict_
                                                        const double *__restrict__ Y, int64_t ldy,
                                                        int64_t n, int p, int q,
                                                        int64_t rows_per_chunk, int nchunks,
-                                                       bool sym, double *__restrict__ ws) {
+                                                       double *__restrict__ ws) {
     __shared__ __align__(16) double Xs[2][BK][PADM];
     __shared__ __align__(16) double Ys[2][BK][PADN];
     const int tiles_j = (q + BN - 1) / BN;
@@ -81,8 +83,6 @@ __global__ __launch_bounds__(256) void gram_f64_kernel(const double *__restrict_
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int wr = w >> 1, wc = w & 1;
     const int i0 = ti * BM, j0 = tj * BN;
-    // symmetric product (X == Y): tiles strictly below the diagonal are mirrored later
-    if (sym && i0 > j0 + BN - 1) return;
     const int lk = lane >> 4, lc = lane & 15;
     const int64_t r0 = (int64_t)chunk * rows_per_chunk;
     const int64_t r1 = min(n, r0 + rows_per_chunk);
@@ -313,24 +313,8 @@ __global__ void expand_c128_kernel(const double *__restrict__ M, int64_t ldm, in
 
 // ---------------------------------------------------------------- host launchers
 
-// Gram workgroups that do work: one round of the chip at 3 workgroups (LDS-bound) per
-// CU, 256 CUs
-constexpr int64_t kGramBlocks = 768;
-
-// Split n rows into chunks so that tiles * chunks is about `target_blocks`; chunk
-// sizes depend only on (n, tiles), which keeps reductions reproducible.
-static void chunking(int64_t n, int64_t tiles, int64_t gran, int64_t target_blocks, int64_t &rows,
-                     int64_t &nchunks) {
-    int64_t want = (target_blocks + tiles - 1) / tiles;
-    const int64_t maxc = (n + 511) / 512;
-    if (want > maxc) want = maxc;
-    if (want < 1) want = 1;
-    rows = (n + want - 1) / want;
-    rows = (rows + gran - 1) / gran * gran;
-    if (rows < gran) rows = gran;
-    nchunks = (n + rows - 1) / rows;
-    if (nchunks < 1) nchunks = 1;
-}
+// Gram workgroups resident at once on one XCD: 32 CUs x 3 (LDS-bound: ~51 KB each).
+constexpr int64_t kGramResidentPerXcd = 96;
 
 // the branch-free pair loads apply: every row of the row-major rows x cols matrix
 // starts on a 16-byte boundary, the column count is even and there is a row
@@ -341,23 +325,25 @@ static bool aligned_pairs(const double *base, int64_t ld, int64_t rows, int64_t 
 
 static void gram_raw(const double *X, int64_t ldx, const double *Y, int64_t ldy, int64_t n,
                      int64_t p, int64_t q, double *G, int64_t ldg, int slot, hipStream_t s) {
+    // X == Y: every tile is still computed (dropping the lower ones left the XCDs
+    // unevenly loaded), and the reduction mirrors the upper triangle so that G is
+    // exactly Hermitian
     const bool sym = X == Y && ldx == ldy && p == q;
-    const int64_t ti = (p + BM - 1) / BM, tj = (q + BN - 1) / BN;
-    int64_t live = ti * tj;  // tiles that do work
-    if (sym) {
-        live = 0;
-        for (int64_t a = 0; a < ti; ++a)
-            for (int64_t b = 0; b < tj; ++b) live += a * BM <= b * BN + BN - 1;
-    }
-    int64_t rows, nchunks;
-    chunking(n, live, BK, kGramBlocks, rows, nchunks);
+    const int64_t ti = (p + BM - 1) / BM, tj = (q + BN - 1) / BN, tiles = ti * tj;
+    // chunks: a multiple of 8 (one per XCD in turn) with at most one resident round
+    // of workgroups per XCD, and at least 512 rows each
+    const int64_t per_xcd = std::max<int64_t>(1, kGramResidentPerXcd / tiles);
+    int64_t want = 8 * per_xcd;
+    want = std::min(want, std::max<int64_t>(1, (n + 511) / 512));
+    int64_t rows = (n + want - 1) / want;
+    rows = std::max<int64_t>(BK, (rows + BK - 1) / BK * BK);
+    const int64_t nchunks = std::max<int64_t>(1, (n + rows - 1) / rows);
     double *ws = (double *)workspace(s).dev_reserve(slot, sizeof(double) * nchunks * p * q);
-    const bool vec = aligned_pairs(X, ldx, n, p) && aligned_pairs(Y, ldy, n, q);
-    const int64_t grid = ti * tj * ((nchunks + 7) / 8 * 8);
+    const int64_t grid = tiles * ((nchunks + 7) / 8 * 8);
     AFSI_REQUIRE(grid < (1LL << 31), "Gram product too large");
+    const bool vec = aligned_pairs(X, ldx, n, p) && aligned_pairs(Y, ldy, n, q);
     hipLaunchKernelGGL(vec ? gram_f64_kernel<true> : gram_f64_kernel<false>, dim3((unsigned)grid),
-                       dim3(256), 0, s, X, ldx, Y, ldy, n, (int)p, (int)q, rows, (int)nchunks, sym,
-                       ws);
+                       dim3(256), 0, s, X, ldx, Y, ldy, n, (int)p, (int)q, rows, (int)nchunks, ws);
     hipLaunchKernelGGL(reduce_chunks_kernel, dim3((unsigned)((p * q + 255) / 256)), dim3(256), 0, s,
                        ws, (int)nchunks, (int)p, (int)q, sym, G, ldg);
     AFSI_HIP(hipGetLastError());
