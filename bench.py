@@ -126,9 +126,8 @@ def main():
     B0 = torch.from_numpy(X0).to(dev)
     del X0
     B1, B2 = torch.empty_like(B0), torch.empty_like(B0)
-    if args.form == "mixed":
-        F0 = torch.empty((n, p), dtype=f32, device=dev)
-        F1, F2 = torch.empty_like(F0), torch.empty_like(F0)
+    F0 = torch.empty((n, p), dtype=f32, device=dev)    # filter blocks of the mixed form
+    F1, F2 = torch.empty_like(F0), torch.empty_like(F0)
     stream = torch.cuda.current_stream()
     if args.calibrate_copy:
         # a plain device copy of one n x p block: reference for the HBM byte counters
@@ -147,8 +146,10 @@ def main():
     # every product of the filter is bracketed by HIP events on this stream
     steady_ms = []   # products that gather src, read V in place and read X (the dominant kernel)
 
+    cur_form = [args.form]
+
     def run_filter(deg):
-        if args.form == "fp64":
+        if cur_form[0] == "fp64":
             ms, kind = afsi.afsi_filter_block_profiled(M.handle, coeffs, deg, B0, B1, B2)
         else:
             afsi.afsi_convert_block(B0, F0)
@@ -194,11 +195,35 @@ def main():
     value = fbytes * args.steps / elapsed / 1e9
     filt_med = float(np.median(filt_ms))
     steady_launch_ms = float(np.mean(steady_ms))
+    steady_launches = len(steady_ms)
     achieved = steady_bytes / (steady_launch_ms * 1e-3) / 1e9
     filter_gbs = fbytes / (filt_med * 1e-3) / 1e9
     log(f"step {ms_per_step:.2f} ms, filter {filt_med:.2f} ms ({filter_gbs:.0f} GB/s), "
-        f"dominant kernel {steady_launch_ms * 1e3:.1f} us avg over {len(steady_ms)} launches ({achieved:.0f} GB/s)")
+        f"dominant kernel {steady_launch_ms * 1e3:.1f} us avg over {steady_launches} launches ({achieved:.0f} GB/s)")
     orth_ms, rr_ms, res_ms = (float(v) for v in np.median(np.array(phase_ms), axis=0))
+
+    # the same iteration in the other form (FP64 filter vs FP32 / complex-FP32 filter;
+    # everything else FP64), same number of steps
+    other = "mixed" if args.form == "fp64" else "fp64"
+    cur_form[0] = other
+    step()
+    torch.cuda.synchronize()
+    filt_ms.clear()
+    phase_ms.clear()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    other_ms = 1e3 * (time.perf_counter() - t1) / args.steps
+    osx = {("fp64", False): 8, ("fp64", True): 16, ("mixed", False): 4, ("mixed", True): 8}[(other, cplx)]
+    other_fbytes, _ = filter_bytes(A.nnz, n, p, osx, osx, coeffs, k)
+    other_rec = {"form": other, "ms_per_step": round(other_ms, 3),
+                 "filter_ms": round(float(np.median(filt_ms)), 3),
+                 "value": round(other_fbytes / (other_ms * 1e-3) / 1e9, 2),
+                 "step_speedup_vs_" + args.form: round(ms_per_step / other_ms, 3)}
+    log(f"{other} form: {other_rec}")
+    cur_form[0] = args.form
+    del F0, F1, F2
 
     # measured copy bandwidth: a plain device copy of one block, same stream, HIP events
     for _ in range(2):
@@ -253,6 +278,7 @@ def main():
         "pct_hbm_peak": round(100.0 * value / HBM_PEAK_GBS, 2),
         "filter_only_gbs": round(filter_gbs, 1),
         "filter_ms": round(filt_med, 3),
+        "other_form": other_rec,
         "phase_ms": {"filter": round(filt_med, 3), "orthonormalize": round(orth_ms, 3),
                      "rayleigh_ritz": round(rr_ms, 3), "residuals": round(res_ms, 3)},
         "measured_copy_gbs": round(copy_gbs, 1),
@@ -261,7 +287,7 @@ def main():
         "dominant_frac_of_3r1w": round(achieved / stream3_gbs, 4),
         "roofline": {
             "kernel": "clenshaw_step_kernel<HAS_V=1,HAS_X=1> (gather src, read V in place, read X, write V)",
-            "launches": len(steady_ms),
+            "launches": steady_launches,
             "bound": "hbm",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
