@@ -88,6 +88,9 @@ def main():
     ap.add_argument("--sweep", default=None, metavar="OUT",
                     help="only measure the filter alone on every workload and precision; "
                          "one JSON line per case into OUT")
+    ap.add_argument("--gather-cost", default=None, metavar="OUT",
+                    help="only measure the steady product on the 100^3 matrix restricted to "
+                         "its diagonal, +-1, +-N and all neighbours; one JSON line per case into OUT")
     args = ap.parse_args()
     if args.cpu_baseline_sweep:
         cpu_sweep(args.cpu_baseline_sweep)   # host only: the oracle on every workload
@@ -109,6 +112,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.sweep:
         filter_sweep(afsi, torch, dev, args.sweep)
+        return
+    if args.gather_cost:
+        gather_cost(afsi, torch, dev, args.gather_cost)
         return
 
     t0 = time.time()
@@ -363,9 +369,57 @@ def filter_sweep(afsi, torch, dev, path, reps=3):
         fh.write(json.dumps(rec) + "\n")
 
 
+def gather_cost(afsi, torch, dev, path, degree=24, reps=3):
+    """What the gathers cost the steady product: the FP64 lap3d_pot_100 matrix (p = 256)
+    restricted to the entries at column offsets {0}, {0, +-1}, {0, +-1, +-N} and all
+    seven, each filtered with the same schedule.  With the diagonal alone the product
+    is a pure 3-read/1-write stream in the kernel's own access pattern; the rate lost
+    with each pair of neighbours is what gathering those rows costs.  Bytes are the
+    compulsory model of each restricted matrix."""
+    from workloads import CSR, build_config, start_block
+
+    A, (lmin, lmax), (a, b), cfg = build_config("lap3d_pot_100", seed=0)
+    n, p = A.n, cfg.p
+    N = round(n ** (1.0 / 3.0))
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(A.row_ptr))
+    off = A.col.astype(np.int64) - rows
+    coeffs = afsi.afsi_filter_coefficients(lmin, lmax, a, b, degree, cfg.damping)
+    X = torch.from_numpy(start_block(n, p, seed=0)).to(dev)
+    Y, W = torch.empty_like(X), torch.empty_like(X)
+    cases = [("diagonal", {0}), ("+-1", {0, 1, -1}), ("+-1,+-N", {0, 1, -1, N, -N}),
+             ("+-1,+-N,+-N^2", {0, 1, -1, N, -N, N * N, -N * N})]
+    with open(path, "w") as fh:
+        for name, offs in cases:
+            keep = np.isin(off, list(offs))
+            counts = np.bincount(rows[keep], minlength=n)
+            rp = np.zeros(n + 1, dtype=np.int64)
+            np.cumsum(counts, out=rp[1:])
+            sub = CSR(n, rp, A.col[keep].copy(), A.val[keep].copy())
+            M = afsi.Matrix(sub, device=0, bounds=(lmin, lmax))
+            _, steady_bytes = filter_bytes(sub.nnz, n, p, 8, 8, coeffs, degree)
+            steady = []
+            for r in range(reps + 1):
+                ms, kind = afsi.afsi_filter_block_profiled(M.handle, coeffs, degree, X, Y, W)
+                if r:
+                    steady.extend(ms[2:][kind[2:] == 3].tolist())
+            sms = float(np.mean(steady))
+            rec = {"workload": "lap3d_pot_100 restricted", "offsets": name, "nnz": sub.nnz, "p": p,
+                   "steady_launch_us": round(sms * 1e3, 2), "bytes_per_steady_launch": steady_bytes,
+                   "steady_gbs": round(steady_bytes / (sms * 1e-3) / 1e9, 1),
+                   "steady_frac_hbm_peak": round(steady_bytes / (sms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            log(f"gather cost {name}: {rec}")
+            fh.write(json.dumps(rec) + "\n")
+            fh.flush()
+            M.close()
+    del X, Y, W
+    torch.cuda.empty_cache()
+
+
 def batched_record(afsi, torch, dev, groups=16, cols=96, launches=30):
     """Batched slice filter: 16 spectrum slices x 96 columns of the 100^3 matrix advanced
     by one launch per step (A read once), against the same groups as 16 launches.
+    `batched`: every group at the same step, so all read one source block;
+    `batched_mixed_sources`: odd groups one step ahead, so the launch mixes two sources.
 
     Every group is in the steady part of its own filter (steps 2..), with its own
     slice coefficients; bytes per launch = A once + per group one pass over each block
@@ -385,8 +439,11 @@ def batched_record(afsi, torch, dev, groups=16, cols=96, launches=30):
     a_bytes = A.nnz * 12 + 4 * (A.n + 1)
     col_pass = A.n * cols * 8
 
-    def step_groups(s):
-        gs = [afsi.afsi_clenshaw_step_params(coeffs[g], k, s, l1, l2, g * cols, cols) for g in range(groups)]
+    def step_groups(s, stagger=0):
+        # stagger = 1: odd groups one step ahead, so neighbouring groups read different
+        # source blocks in the same launch
+        gs = [afsi.afsi_clenshaw_step_params(coeffs[g], k, s + stagger * (g % 2), l1, l2, g * cols, cols)
+              for g in range(groups)]
         for g in gs:
             g.active = 1
         return gs
@@ -400,14 +457,14 @@ def batched_record(afsi, torch, dev, groups=16, cols=96, launches=30):
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     out = {"workload": "lap3d_pot_100 slices", "kernel": "clenshaw_batched_kernel", "groups": groups,
            "cols_per_group": cols, "n": A.n, "degree": k, "launches": launches}
-    for mode in ("batched", "one_launch_per_group"):
+    for mode in ("batched", "batched_mixed_sources", "one_launch_per_group"):
         steps = list(range(2, 2 + launches))
         total = 0
         for warm in (True, False):
             ev[0].record()
             for s in steps:
-                gs = step_groups(s)
-                if mode == "batched":
+                gs = step_groups(s, 1 if mode == "batched_mixed_sources" else 0)
+                if mode != "one_launch_per_group":
                     afsi.afsi_clenshaw_step_batched(M.handle, gs, X, P0, P1)
                     total += bytes_of(gs, True)
                 else:

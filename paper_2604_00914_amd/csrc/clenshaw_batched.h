@@ -13,7 +13,11 @@ namespace afsi {
 // A vector belongs to the group whose [vec0, vec1) holds it; vectors outside every
 // active group are left untouched (their products are computed and discarded, so
 // that the gather loop is the same for every lane).  At least 4 waves per SIMD.
-template <class Tr, int VN, int U>
+// SAME_SRC: every active group reads the same source block (the host checks), so the
+// gathers use one wave-uniform base address instead of a per-lane pointer, which the
+// address unit handles as a scalar base plus a 32-bit lane offset (16 slices x 96
+// columns of the 100^3 matrix: 13.2 against 14.8 ms per step).
+template <class Tr, int VN, int U, bool SAME_SRC>
 __global__ __launch_bounds__(256, 4) void clenshaw_batched_kernel(
     int n, const int *__restrict__ rp, const int *__restrict__ ci,
     const typename Tr::val *__restrict__ va, const typename Tr::vec *__restrict__ X,
@@ -45,7 +49,7 @@ __global__ __launch_bounds__(256, 4) void clenshaw_batched_kernel(
         grp[v] = -1;
         for (int g = 0; g < args.ngroups; ++g)
             if (vi >= args.vec0[g] && vi < args.vec1[g]) grp[v] = g;
-        const int s = grp[v] >= 0 ? args.src[grp[v]] : 0;
+        const int s = SAME_SRC ? args.src[0] : (grp[v] >= 0 ? args.src[grp[v]] : 0);
         sp[v] = s == 0 ? X : (s == 1 ? P0 : P1);
         vix[v] = grp[v] >= 0 ? vi : args.vec0[0];
         live |= (grp[v] >= 0) << v;
@@ -90,7 +94,7 @@ __global__ __launch_bounds__(256, 4) void clenshaw_batched_kernel(
     }
 }
 
-template <class Tr, int VN>
+template <class Tr, int VN, bool SAME_SRC>
 void launch_batched(const MatView &A, const void *X, void *P0, void *P1, int p16, int64_t ldv,
                     const BatchArgs &args, hipStream_t s) {
     using vec = typename Tr::vec;
@@ -98,9 +102,10 @@ void launch_batched(const MatView &A, const void *X, void *P0, void *P1, int p16
     const int64_t items = A.n * (int64_t)nchunks;
     AFSI_REQUIRE(items < (1LL << 31), "batched step: rows x column chunks too large");
     const Grid g = xcd_grid(items, 4);  // 4 items (waves) per workgroup
-    hipLaunchKernelGGL((clenshaw_batched_kernel<Tr, VN, 8>), dim3((unsigned)g.grid), dim3(256), 0, s,
-                       (int)A.n, A.rp, A.ci, (const typename Tr::val *)A.val, (const vec *)X,
-                       (vec *)P0, (vec *)P1, ldv, p16, nchunks, g.group, g.nblocks, args);
+    hipLaunchKernelGGL((clenshaw_batched_kernel<Tr, VN, 8, SAME_SRC>), dim3((unsigned)g.grid),
+                       dim3(256), 0, s, (int)A.n, A.rp, A.ci, (const typename Tr::val *)A.val,
+                       (const vec *)X, (vec *)P0, (vec *)P1, ldv, p16, nchunks, g.group, g.nblocks,
+                       args);
 }
 
 // 2 vectors per lane (2 KB chunks of an FP64 row): on 16 slices x 96 columns of the
@@ -108,7 +113,10 @@ void launch_batched(const MatView &A, const void *X, void *P0, void *P1, int p16
 template <class Tr>
 void dispatch_batched(const MatView &A, const void *X, void *P0, void *P1, int p16, int64_t ldv,
                       const BatchArgs &args, hipStream_t s) {
-    launch_batched<Tr, 2>(A, X, P0, P1, p16, ldv, args, s);
+    bool same = true;
+    for (int g = 1; g < args.ngroups; ++g) same = same && args.src[g] == args.src[0];
+    if (same) launch_batched<Tr, 2, true>(A, X, P0, P1, p16, ldv, args, s);
+    else launch_batched<Tr, 2, false>(A, X, P0, P1, p16, ldv, args, s);
 }
 
 }  // namespace afsi

@@ -64,6 +64,9 @@ struct Session {
     std::vector<double> coeffs;
     double l1 = 0, l2 = 0, tau_abs = 0;
     int k_cur = 1, step = 0, phase = PH_INIT;
+    // the filter's two product blocks exchanged (chosen when the filter starts, so that
+    // every filtering session reads its source from the same block in each launch)
+    int swap = 0;
     int64_t n_check_prev = 0;
     std::vector<int> degrees;
 };
@@ -81,6 +84,7 @@ struct Pool {
     std::vector<uint8_t> used;  // per column
     std::list<Session> sessions;
     std::deque<Session> incoming;
+    int64_t rounds = 0;  // batched rounds issued, each one step of every filtering session
     size_t bytes = 0;
     bool mixed() const { return fdt != dt; }
 };
@@ -306,7 +310,8 @@ int dense_phase(Pool *P, Session &s) {
     Request *r = s.r;
     const int dt = P->dt;
     const int64_t n = P->n, ld = P->cap, pa = s.p_act;
-    const int outi = 1 + (s.k_cur - 1) % 2;  // product output lands in P[(k-1) % 2]
+    // the last product's output block: 1 + (k-1) % 2, or the other one when swapped
+    const int outi = s.swap ? 2 - (s.k_cur - 1) % 2 : 1 + (s.k_cur - 1) % 2;
     void *q, *w;
     if (P->mixed()) {
         afsi_block src{col_ptr(P->F[outi], s.col0, P->fdt), n, pa, ld, P->fdt};
@@ -451,6 +456,14 @@ void pool_thread(Pool *P) {
             if (s.phase == PH_FILTER) {
                 afsi_step_group g{};
                 step_params(s.coeffs.data(), s.k_cur, s.step, s.l1, s.l2, &g);
+                // step s >= 1 reads block 1 + (s-1) % 2; a filter starting in an even round
+                // exchanges the two blocks, so that every filter past its first step reads
+                // block 1 + rounds % 2 and the batched product gathers from one block
+                if (s.step == 0) s.swap = P->rounds % 2 == 0;
+                if (s.swap) {
+                    if (g.src != 0) g.src = 3 - g.src;
+                    g.dst = 3 - g.dst;
+                }
                 g.col0 = s.col0;
                 g.ncols = round_up(s.p_act, P->E);
                 g.active = 1;
@@ -477,6 +490,7 @@ void pool_thread(Pool *P) {
             P->sessions.remove_if([](const Session &s) { return s.phase == -1; });
             continue;
         }
+        if (!groups.empty()) ++P->rounds;
         for (auto *s : filt)
             if (++s->step == s->k_cur) s->phase = PH_DENSE;
         for (auto it = P->sessions.begin(); it != P->sessions.end(); ++it) {

@@ -178,6 +178,9 @@ BATCH_LAYOUTS = {
     # wide: 300 vectors per row (4 per lane, ragged second chunk), columns 200..209 and
     # 546..599 in no group
     "wide": (600, [(0, 200, 7, (3.0, 3.5), 0), (210, 328, 12, (5.0, 5.3), 2), (538, 8, 5, (9.0, 11.0), 4)]),
+    # groups one step apart read different source blocks in the same launch (the general
+    # kernel); launches where every active group reads one block take the same-source kernel
+    "parity": (256, [(0, 64, 9, (3.0, 3.5), 0), (64, 96, 10, (5.0, 5.3), 1), (160, 96, 6, (9.0, 11.0), 3)]),
 }
 
 
