@@ -307,6 +307,7 @@ def main():
 
     if not args.no_solve:
         out["solve"] = solve_rates(afsi, torch, dev)
+        out["eigencount"] = eigencount_rates(afsi, torch, dev)
     if not args.no_serve:
         out["serve"] = serve_rates(afsi, M, args.serve_requests)
 
@@ -563,6 +564,38 @@ def solve_rates(afsi, torch, dev):
                     rec_w[fast]["eigenpairs_per_s"] / rec_w[slow]["eigenpairs_per_s"], 3)
         M.close()
         out[name] = rec_w
+    return out
+
+
+def eigencount_rates(afsi, torch, dev, probes=64):
+    """Setup step of Section 3.4: the eigenvalue count in [a, b] by trace estimation of
+    the filter (Lanczos damping m = 0.5 at the workload's degree) over `probes` +-1
+    probe vectors, and the block size p = ceil(1.8 * estimate) it implies.  Reports the
+    estimate, its standard error, the exact count where a fixture holds it, and the
+    wall time of the call (inputs resident)."""
+    from workloads import build_config, probe_block
+
+    out = {}
+    for name in ("lap2d_64", "lap3d_pot_27", "lap3d_pot_100"):
+        A, (lmin, lmax), (a, b), cfg = build_config(name)
+        M = afsi.Matrix(A, device=0, bounds=(lmin, lmax))
+        Z = torch.from_numpy(probe_block(A.n, probes, seed=1)).to(dev)
+        Y, W = torch.empty_like(Z), torch.empty_like(Z)
+        afsi.afsi_estimate_eigencount(M.handle, a, b, cfg.degree, Z, Y, W, "lanczos", 0.5)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        est, per = afsi.afsi_estimate_eigencount(M.handle, a, b, cfg.degree, Z, Y, W, "lanczos", 0.5)
+        dt = time.perf_counter() - t0
+        rec = {"n": A.n, "degree": cfg.degree, "probes": probes, "estimate": round(est, 2),
+               "std_error": round(float(np.std(per, ddof=1) / np.sqrt(per.size)), 2),
+               "block_size": int(np.ceil(1.8 * est)), "configured_p": cfg.p, "ms": round(dt * 1e3, 2)}
+        if name != "lap3d_pot_100":
+            rec["exact_count"] = int(_window_fixture(name).size)
+        log(f"eigencount {name}: {rec}")
+        out[name] = rec
+        del Z, Y, W
+        M.close()
+        torch.cuda.empty_cache()
     return out
 
 

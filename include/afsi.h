@@ -148,6 +148,26 @@ int afsi_filter_block_profiled(afsi_matrix_t A, const double *coeffs, int degree
                                const afsi_block *X, afsi_block *Y, afsi_block *work, void *stream,
                                float *step_ms, int32_t *step_kind);
 
+/*
+ * Eigenvalue count of A in [a, b] by stochastic trace estimation (Section 3.4).  The
+ * damped filter rho(x) = sum_{j=0}^{degree} c_j d_{j,degree} T_j(l(x)) of eq.
+ * (AdaPolySI) at its full degree approximates the spectral projector onto [a, b], so
+ * the count is close to tr rho(A), estimated by the mean of Re z_i^H rho(A) z_i over
+ * the m columns z_i of Z (Hutchinson's estimator).  The caller draws Z (for example
+ * independent +-1 entries), so the result does not depend on a generator inside the
+ * library.  The paper then sizes the block as p = ceil(mu * estimate), mu = 1.8.
+ *   Z         : n x m device block, R64 for a real A, C128 for a complex A; read only.
+ *   Y, work   : n x m device blocks of Z's dtype, overwritten (Y = rho(A) Z).
+ *   damping   : AFSI_DAMP_*; m_exp the Lanczos exponent (paper: 0.5).
+ *   per_probe : host, m doubles: Re z_i^H rho(A) z_i.
+ *   estimate  : host: their mean.
+ * Needs spectral bounds on A, a < b, degree >= 1, m >= 1; Z, Y and work must not
+ * overlap.  Errors: AFSI_E_INVALID.  Synchronises `stream`.
+ */
+int afsi_estimate_eigencount(afsi_matrix_t A, double a, double b, int degree, int32_t damping,
+                             double m_exp, const afsi_block *Z, afsi_block *Y, afsi_block *work,
+                             double *per_probe, double *estimate, void *stream);
+
 /* Y = A X (one sparse x dense-block product). X and Y as for afsi_filter_block. */
 int afsi_spmm(afsi_matrix_t A, const afsi_block *X, afsi_block *Y, void *stream);
 

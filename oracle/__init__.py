@@ -21,4 +21,5 @@ solver        the full adaptive filtered subspace iteration with locking
 closed_form   grid-Laplacian spectra (definition-level results)
 spectra       eigenvalues of a banded real symmetric matrix inside an interval
 bounds        Lanczos estimate of the spectral interval
+eigencount    eigenvalue count in [a, b] by trace estimation of the filter
 """

@@ -87,6 +87,7 @@ _SIGS = {
     "afsi_filter_coefficients": (C.c_int, [C.c_double, C.c_double, C.c_double, C.c_double, C.c_int, C.c_int32, C.c_double, _P]),
     "afsi_filter_block": (C.c_int, [_P, _P, C.c_int, _BP, _BP, _BP, _P]),
     "afsi_filter_block_profiled": (C.c_int, [_P, _P, C.c_int, _BP, _BP, _BP, _P, _P, _P]),
+    "afsi_estimate_eigencount": (C.c_int, [_P, C.c_double, C.c_double, C.c_int, C.c_int32, C.c_double, _BP, _BP, _BP, _P, _DP, _P]),
     "afsi_spmm": (C.c_int, [_P, _BP, _BP, _P]),
     "afsi_clenshaw_step_params": (C.c_int, [_P, C.c_int, C.c_int, C.c_double, C.c_double, C.POINTER(afsi_step_group)]),
     "afsi_clenshaw_step_batched": (C.c_int, [_P, C.c_int, C.POINTER(afsi_step_group), _BP, _BP, _BP, _P]),
@@ -256,6 +257,16 @@ def afsi_filter_block_profiled(h, coeffs, degree: int, X, Y, work, stream=None):
     _check(lib().afsi_filter_block_profiled(h, _ptr(c), degree, _bref(_blk(X)), _bref(_blk(Y)), _bref(_blk(work)),
                                             _stream(stream), _ptr(ms), _ptr(kind)))
     return ms, kind
+
+
+def afsi_estimate_eigencount(h, a, b, degree: int, Z, Y, work, damping="lanczos", m_exp=0.5, stream=None):
+    """Returns (estimate, per_probe[m]): mean and values of Re z_i^H rho(A) z_i."""
+    z = _blk(Z)
+    per = np.empty(z.cols, dtype=np.float64)
+    est = C.c_double(0.0)
+    _check(lib().afsi_estimate_eigencount(h, a, b, degree, _DAMPING.get(damping, damping), m_exp, _bref(z),
+                                          _bref(_blk(Y)), _bref(_blk(work)), _ptr(per), C.byref(est), _stream(stream)))
+    return est.value, per
 
 
 def afsi_spmm(h, X, Y, stream=None):

@@ -554,6 +554,47 @@ int afsi_spmm(afsi_matrix_t A, const afsi_block *X, afsi_block *Y, void *stream)
     });
 }
 
+int afsi_estimate_eigencount(afsi_matrix_t A, double a, double b, int degree, int32_t damping,
+                             double m_exp, const afsi_block *Z, afsi_block *Y, afsi_block *work,
+                             double *per_probe, double *estimate, void *stream) {
+    return guarded([&] {
+        check_matrix(A);
+        AFSI_REQUIRE(per_probe != nullptr && estimate != nullptr, "NULL per_probe / estimate");
+        AFSI_REQUIRE(A->has_bounds, "spectral bounds of A are not set");
+        check_block(Z, "Z");
+        check_block(Y, "Y");
+        check_block(work, "work");
+        check_fp64(Z, "Z");
+        check_same_shape(Z, Y, "Z", "Y");
+        check_same_shape(Z, work, "Z", "work");
+        AFSI_REQUIRE(Z->rows == A->n, "Z has %lld rows, A has %lld", (long long)Z->rows,
+                     (long long)A->n);
+        AFSI_REQUIRE(Z->cols >= 1, "Z needs at least one probe column");
+        AFSI_REQUIRE(!overlap(Z, Y) && !overlap(Z, work) && !overlap(Y, work),
+                     "Z, Y and work must not overlap");
+        AFSI_REQUIRE(degree >= 1, "degree must be >= 1 (got %d)", degree);
+        // the damped filter of eq. (AdaPolySI) at its full degree, as the paper's projector
+        std::vector<double> c(degree + 1);
+        filter_coefficients(A->lmin, A->lmax, a, b, degree, damping, m_exp, c.data());
+        DeviceGuard dg(A->device);
+        hipStream_t s = as_stream(stream);
+        filter_apply(A, c.data(), degree, Z->dtype, Z->ptr, Y->ptr, work->ptr, Z->cols, Z->ld, s);
+        const int64_t m = Z->cols;
+        Workspace &ws = workspace(s);
+        double *d = (double *)ws.dev_reserve(SLOT_VEC, sizeof(double) * m);
+        column_dots_dev(Z->dtype, Z->ptr, Z->ld, Y->ptr, Y->ld, Z->rows, m, d, s);
+        double *h = (double *)ws.host_reserve(1, sizeof(double) * m);
+        AFSI_HIP(hipMemcpyAsync(h, d, sizeof(double) * m, hipMemcpyDeviceToHost, s));
+        AFSI_HIP(hipStreamSynchronize(s));
+        double sum = 0.0;
+        for (int64_t i = 0; i < m; ++i) {
+            per_probe[i] = h[i];
+            sum += h[i];
+        }
+        *estimate = sum / (double)m;
+    });
+}
+
 int afsi_clenshaw_step_params(const double *coeffs, int degree, int step, double l1, double l2,
                               afsi_step_group *g) {
     return guarded([&] {

@@ -1,4 +1,5 @@
-// Column reductions for the residual step (Algorithm 4) and the shifted Cholesky QR.
+// Column reductions for the residual step (Algorithm 4), the shifted Cholesky QR and
+// the eigenvalue-count estimate (Section 3.4).
 //
 // colsq: per column j, sum_i |AV[i, j] - lambda_j V[i, j]|^2 (V may be absent: |AV|^2).
 // Each block owns 64 columns and a chunk of rows; its 4 row-lanes are combined in a
@@ -38,6 +39,37 @@ __global__ __launch_bounds__(256) void colsq_partial_kernel(const double *__rest
                 double d = AV[i * ldav + col];
                 if (V) d = __builtin_fma(-l, V[i * ldv + col], d);
                 s = __builtin_fma(d, d, s);
+            }
+        }
+    }
+    red[r][c] = s;
+    __syncthreads();
+    if (r == 0 && col < q)
+        ws[(int64_t)blockIdx.x * q + col] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+}
+
+// coldot: per column j, Re sum_i conj(Z[i, j]) Y[i, j]; same chunking and fixed-order
+// combination as colsq.
+template <bool CPLX>
+__global__ __launch_bounds__(256) void coldot_partial_kernel(const double *__restrict__ Z, int64_t ldz,
+                                                             const double *__restrict__ Y, int64_t ldy,
+                                                             int64_t n, int q, int64_t rows_per_chunk,
+                                                             double *__restrict__ ws) {
+    __shared__ double red[4][64];
+    const int r = threadIdx.x >> 6, c = threadIdx.x & 63;
+    const int col = blockIdx.y * 64 + c;
+    const int64_t i0 = (int64_t)blockIdx.x * rows_per_chunk;
+    const int64_t i1 = min(n, i0 + rows_per_chunk);
+    double s = 0.0;
+    if (col < q) {
+        for (int64_t i = i0 + r; i < i1; i += 4) {
+            if (CPLX) {
+                const double *z = Z + 2 * (i * ldz + col);
+                const double *y = Y + 2 * (i * ldy + col);
+                s = __builtin_fma(z[0], y[0], s);
+                s = __builtin_fma(z[1], y[1], s);
+            } else {
+                s = __builtin_fma(Z[i * ldz + col], Y[i * ldy + col], s);
             }
         }
     }
@@ -99,6 +131,21 @@ void residual_norms_dev(int dtype, const void *V, int64_t ldv, const void *AV, i
                         const double *d_lambda, int64_t n, int64_t q, double *d_norms,
                         hipStream_t s) {
     colsq(dtype, V, ldv, AV, ldav, d_lambda, n, q, true, d_norms, s);
+}
+
+void column_dots_dev(int dtype, const void *Z, int64_t ldz, const void *Y, int64_t ldy, int64_t n,
+                     int64_t q, double *d_out, hipStream_t s) {
+    if (q == 0) return;
+    const int64_t ctiles = (q + 63) / 64;
+    int64_t rows, nchunks;
+    chunking(n, ctiles, 4, 1024, rows, nchunks);
+    double *ws = (double *)workspace(s).dev_reserve(SLOT_PARTIAL, sizeof(double) * nchunks * q);
+    auto kern = dtype == AFSI_C128 ? coldot_partial_kernel<true> : coldot_partial_kernel<false>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)nchunks, (unsigned)ctiles), dim3(256), 0, s,
+                       (const double *)Z, ldz, (const double *)Y, ldy, n, (int)q, rows, ws);
+    hipLaunchKernelGGL(colsq_finalize_kernel, dim3((unsigned)((q + 255) / 256)), dim3(256), 0, s, ws,
+                       (int)nchunks, (int)q, false, d_out);
+    AFSI_HIP(hipGetLastError());
 }
 
 void frob2_dev(int dtype, const void *X, int64_t ldx, int64_t n, int64_t q, double *d_out,

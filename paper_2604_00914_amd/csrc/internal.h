@@ -184,6 +184,9 @@ void gemm_c128(const double *X, int64_t ldx, const double *M, int64_t ldm, int64
 void residual_norms_dev(int dtype, const void *V, int64_t ldv, const void *AV, int64_t ldav,
                         const double *d_lambda, int64_t n, int64_t q, double *d_norms,
                         hipStream_t s);
+// d_out[j] = Re sum_i conj(Z[i, j]) Y[i, j], device output (q doubles).  R64 or C128.
+void column_dots_dev(int dtype, const void *Z, int64_t ldz, const void *Y, int64_t ldy, int64_t n,
+                     int64_t q, double *d_out, hipStream_t s);
 // ||X||_F^2 per column summed: device scalar.
 void frob2_dev(int dtype, const void *X, int64_t ldx, int64_t n, int64_t q, double *d_out,
                hipStream_t s);

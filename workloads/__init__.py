@@ -14,7 +14,7 @@ from .matrices import (
     random_dense_symmetric_csr,
     gershgorin_bounds,
 )
-from .blocks import start_block
+from .blocks import probe_block, start_block
 from .configs import CONFIGS, WorkloadConfig, build_config
 
 __all__ = [
@@ -25,6 +25,7 @@ __all__ = [
     "random_banded_symmetric",
     "random_dense_symmetric_csr",
     "gershgorin_bounds",
+    "probe_block",
     "start_block",
     "CONFIGS",
     "WorkloadConfig",

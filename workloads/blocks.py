@@ -15,3 +15,14 @@ def start_block(n: int, p: int, seed: int = 0, complex_: bool = False) -> np.nda
     re = rng.standard_normal((n, p))
     im = rng.standard_normal((n, p))
     return (re + 1j * im) / np.sqrt(2.0)
+
+
+def probe_block(n: int, m: int, seed: int = 0, complex_: bool = False) -> np.ndarray:
+    """m probe vectors for trace estimation: independent +-1 entries from ``default_rng(seed)``
+    (complex: (+-1 +- i)/sqrt(2)), so that E[z z^H] = I.  C-contiguous n x m."""
+    rng = np.random.default_rng(seed)
+    re = rng.integers(0, 2, size=(n, m)) * 2.0 - 1.0
+    if not complex_:
+        return re
+    im = rng.integers(0, 2, size=(n, m)) * 2.0 - 1.0
+    return (re + 1j * im) / np.sqrt(2.0)
