@@ -88,6 +88,9 @@ def main():
     ap.add_argument("--sweep", default=None, metavar="OUT",
                     help="only measure the filter alone on every workload and precision; "
                          "one JSON line per case into OUT")
+    ap.add_argument("--sensitivity", default=None, metavar="OUT",
+                    help="only run the parameter-sensitivity solves (damping exponent m, "
+                         "tau_a, C_r adaptive vs fixed); one JSON line per solve into OUT")
     ap.add_argument("--gather-cost", default=None, metavar="OUT",
                     help="only measure the steady product on the 100^3 matrix restricted to "
                          "its diagonal, +-1, +-N and all neighbours; one JSON line per case into OUT")
@@ -115,6 +118,9 @@ def main():
         return
     if args.gather_cost:
         gather_cost(afsi, torch, dev, args.gather_cost)
+        return
+    if args.sensitivity:
+        sensitivity(afsi, torch, dev, args.sensitivity)
         return
 
     t0 = time.time()
@@ -370,6 +376,64 @@ def filter_sweep(afsi, torch, dev, path, reps=3):
         fh.write(json.dumps(rec) + "\n")
 
 
+def sensitivity(afsi, torch, dev, path, max_iter=400):
+    """Parameter sensitivity of the adaptive solver (the experiments of Section 4.2, on
+    synthetic matrices): the damping exponent m in [0, 3] step 0.1 and tau_a in
+    [1e-4, 0.5] with k^(1) from eq. (compute_k_1) (C = 1.4) and k = ceil(2.5 k^(1));
+    then C_r = C / (alpha - beta) over 13 values in [10, 120], k^(1) = ceil(C_r) - 1,
+    for the adaptive filter (k = ceil(2.5 k^(1))) and for the fixed degree k^(1).
+    Workloads: lap3d_pot_27 (196 eigenvalues) and lap2d_64 (40), FP64, tau_c = 1e-10.
+    Per solve: wall time, iterations, average degree, products with A, the filter's and
+    the other phases' time, and whether the count and every eigenvalue are right."""
+    from workloads import build_config, start_block
+
+    with open(path, "w") as fh:
+        for name in ("lap3d_pot_27", "lap2d_64"):
+            A, (lmin, lmax), (a, b), cfg = build_config(name)
+            exact = _window_fixture(name)
+            normA = max(abs(lmin), abs(lmax))
+            M = afsi.Matrix(A, device=0, bounds=(lmin, lmax))
+            X0 = start_block(A.n, cfg.p, seed=0)
+            k1_paper = paper_initial_degree(lmin, lmax, a, b)
+
+            def run(study, value, k1, kmax, adaptive, m_exp=0.5, tau_a=1e-3):
+                o = afsi.afsi_options_default(kmax)
+                o.k_init = k1
+                o.adaptive = adaptive
+                o.damping = afsi.DAMP_LANCZOS
+                o.m_exp = m_exp
+                o.tau_a = tau_a
+                o.max_iter = max_iter
+                X = torch.from_numpy(X0).to(dev)
+                E = torch.zeros((A.n, cfg.p), dtype=torch.float64, device=dev)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st, lam, res, r = afsi.afsi_solve(M.handle, a, b, o, X, E, cfg.p)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                ok = bool(st == 0 and lam.size == exact.size and np.max(np.abs(lam - exact)) <= 1e-10 * normA)
+                other = r.time_orth_ms + r.time_rr_ms + r.time_resid_ms + r.time_host_ms
+                rec = {"workload": name, "study": study, "value": value, "adaptive": adaptive,
+                       "k1": k1, "kmax": kmax, "m_exp": m_exp, "tau_a": tau_a, "status": st,
+                       "correct": ok, "seconds": round(dt, 4), "iterations": r.iterations,
+                       "avg_degree": round(r.avg_degree, 2), "spmv": r.spmv,
+                       "filter_ms": round(r.time_filter_ms, 2), "other_ms": round(other, 2)}
+                log(f"sensitivity {name} {study}={value} adaptive={adaptive}: {rec}")
+                fh.write(json.dumps(rec) + "\n")
+                fh.flush()
+
+            kmax_paper = math.ceil(2.5 * k1_paper)
+            for i in range(31):
+                run("m", round(0.1 * i, 1), k1_paper, kmax_paper, 1, m_exp=0.1 * i)
+            for ta in (1e-4, 3e-4, 1e-3, 3e-3, 1e-2, 3e-2, 1e-1, 5e-1):
+                run("tau_a", ta, k1_paper, kmax_paper, 1, tau_a=ta)
+            for cr in np.linspace(10.0, 120.0, 13):
+                k1 = max(1, math.ceil(cr) - 1)
+                run("C_r", round(float(cr), 2), k1, math.ceil(2.5 * k1), 1)
+                run("C_r", round(float(cr), 2), k1, k1, 0)
+            M.close()
+
+
 def gather_cost(afsi, torch, dev, path, degree=24, reps=3):
     """What the gathers cost the steady product: the FP64 lap3d_pot_100 matrix (p = 256)
     restricted to the entries at column offsets {0}, {0, +-1}, {0, +-1, +-N} and all
@@ -508,12 +572,22 @@ SOLVE_MODES = [
 ]
 
 
+def paper_initial_degree(lmin, lmax, a, b, C=1.4):
+    """k^(1) = ceil(C / (alpha - beta)) - 1 of eq. (compute_k_1), alpha = arccos l(a),
+    beta = arccos l(b) with l(.) clipped into [-1, 1] (the experiment's parameter, as the
+    solver computes it when it is not given)."""
+    t = lambda x: min(1.0, max(-1.0, (2 * x - lmax - lmin) / (lmax - lmin)))
+    return max(1, math.ceil(C / (math.acos(t(a)) - math.acos(t(b)))) - 1)
+
+
 def solve_rates(afsi, torch, dev):
     """Eigenpairs/s of the full solver on the converging workloads, FP64 vs mixed.
 
     lap2d_64 (40 eigenvalues, closed form) and lap3d_pot_27 (196 eigenvalues from the
-    banded eigensolver), each from its stored fixture.  Modes: fixed Jackson degree and
-    the paper's adaptive mode (Lanczos damping m = 0.5, Algorithm 3 degree); FP64 at
+    banded eigensolver), each from its stored fixture.  Modes: fixed Jackson degree (the
+    workload's) and the paper's adaptive mode (Section 4: Lanczos damping m = 0.5,
+    tau_a = 1e-3, k^(1) from eq. (compute_k_1) with C = 1.4, maximum degree
+    k = ceil(2.5 k^(1)), Algorithm 3 after every iteration); FP64 at
     tau_c = 1e-10 (full accuracy) and at tau_c = 1e-6 (the mixed form's accuracy, for an
     equal-accuracy comparison).  A run counts its eigenpairs only if the count is exact
     and every eigenvalue is within 1e-10 ||A|| (tau_c 1e-10) or 1e-5 ||A|| (tau_c 1e-6).
@@ -529,8 +603,10 @@ def solve_rates(afsi, torch, dev):
         M = afsi.Matrix(A, device=0, bounds=(lmin, lmax))
         X0 = start_block(A.n, cfg.p, seed=0)
         rec_w = {"n": A.n, "p": cfg.p, "degree": cfg.degree, "eigenvalues": int(exact.size)}
+        k1 = paper_initial_degree(lmin, lmax, a, b)
+        rec_w["adaptive_k1_kmax"] = [k1, math.ceil(2.5 * k1)]
         for label, form, tau_c, adaptive in SOLVE_MODES:
-            o = afsi.afsi_options_default(cfg.degree)
+            o = afsi.afsi_options_default(math.ceil(2.5 * k1) if adaptive else cfg.degree)
             o.max_iter = 1500
             o.tau_c = tau_c
             if form == "mixed":
