@@ -257,3 +257,35 @@ def test_full_size_config2_low_degree_vs_oracle():
     got = gpu_filter(A, X0, lmin, lmax, c, 3)
     ref = oracle_filter(A, X0, lmin, lmax, a, b, 3)
     _check(got, ref, F64_TOL)
+
+
+def _gpu_filter_columns(M, X0, coeffs, degree, single, cols):
+    """Filter the whole block on the GPU (the launch configuration the benchmark times)
+    and return only the requested columns."""
+    t = torch()
+    dt = _tdt(np.iscomplexobj(X0), single)
+    X = t.from_numpy(X0).to(DEV).to(dt)
+    Y, W = t.empty_like(X), t.empty_like(X)
+    afsi.afsi_filter_block(M.handle, coeffs, degree, X, Y, W)
+    t.cuda.synchronize()
+    out = Y[:, cols].cpu().numpy().astype(np.complex128 if np.iscomplexobj(X0) else np.float64)
+    del X, Y, W
+    t.cuda.empty_cache()
+    return out
+
+
+@pytest.mark.parametrize("name,cols", [("lap3d_pot_100", [0, 101, 255]), ("tb3d_64", [0, 77, 191]),
+                                       ("rand_2m", [0, 639])])
+def test_full_size_sampled_columns(name, cols):
+    # full n, p and degree of the workload, both precisions: the filter acts on every
+    # column separately, so sampled columns of the GPU's block equal the oracle's filter
+    # of those columns of the start block
+    A, (lmin, lmax), (a, b), cfg = build_config(name)
+    X0 = start_block(A.n, cfg.p, seed=0, complex_=A.is_complex)
+    c = afsi.afsi_filter_coefficients(lmin, lmax, a, b, cfg.degree, cfg.damping)
+    ref = oracle_filter(A, np.ascontiguousarray(X0[:, cols]), lmin, lmax, a, b, cfg.degree, cfg.damping)
+    M = afsi.Matrix(A, bounds=(lmin, lmax))
+    for single in (False, True):
+        got = _gpu_filter_columns(M, X0, c, cfg.degree, single, cols)
+        _check(got, ref, f32_tol(cfg.degree) if single else F64_TOL)
+    M.close()
