@@ -289,3 +289,38 @@ def test_full_size_sampled_columns(name, cols):
         got = _gpu_filter_columns(M, X0, c, cfg.degree, single, cols)
         _check(got, ref, f32_tol(cfg.degree) if single else F64_TOL)
     M.close()
+
+
+@pytest.mark.parametrize("stagger", [0, 1])
+def test_full_size_batched_slices_sampled_columns(stagger):
+    # the batched step at full size (16 slices x 96 columns of the 100^3 matrix, degree
+    # 120, each slice with its own coefficients); stagger 0: every launch reads one source
+    # block; stagger 1: odd slices one step behind, so launches mix source blocks; one
+    # sampled column per slice against the oracle's filter of that column
+    from workloads.stream import slice_intervals
+
+    t = torch()
+    A, (lo, hi), _, cfg = build_config("lap3d_pot_100")
+    k, G, cols = cfg.degree, 16, 96
+    l1, l2 = co.affine_map(lo, hi)
+    ivs = slice_intervals(A.n, 0.5 * (lo + hi), G, 50)
+    coeffs = [afsi.afsi_filter_coefficients(lo, hi, a, b, k, "jackson") for a, b in ivs]
+    X0 = start_block(A.n, G * cols, seed=0)
+    M = afsi.Matrix(A, bounds=(lo, hi))
+    X = to_dev(X0)
+    P0, P1 = t.zeros_like(X), t.zeros_like(X)
+    for step in range(k + stagger):
+        gs = [afsi.afsi_clenshaw_step_params(coeffs[g], k, step - stagger * (g % 2), l1, l2, col0=g * cols,
+                                             ncols=cols)
+              for g in range(G) if 0 <= step - stagger * (g % 2) < k]
+        afsi.afsi_clenshaw_step_batched(M.handle, gs, X, P0, P1)
+    t.cuda.synchronize()
+    out = P0 if (k - 1) % 2 == 0 else P1
+    pick = [g * cols + (7 * g) % cols for g in range(G)]
+    got = out[:, pick].cpu().numpy()
+    del X, P0, P1
+    t.cuda.empty_cache()
+    M.close()
+    for j, g in enumerate(range(G)):
+        ref = clenshaw_filter(A, np.ascontiguousarray(X0[:, pick[j]:pick[j] + 1]), coeffs[g], l1, l2)
+        _check(got[:, j:j + 1], ref, F64_TOL)
