@@ -580,7 +580,7 @@ def paper_initial_degree(lmin, lmax, a, b, C=1.4):
     return max(1, math.ceil(C / (math.acos(t(a)) - math.acos(t(b)))) - 1)
 
 
-def solve_rates(afsi, torch, dev):
+def solve_rates(afsi, torch, dev, seeds=(0, 1, 2, 3, 4)):
     """Eigenpairs/s of the full solver on the converging workloads, FP64 vs mixed.
 
     lap2d_64 (40 eigenvalues, closed form) and lap3d_pot_27 (196 eigenvalues from the
@@ -591,20 +591,33 @@ def solve_rates(afsi, torch, dev):
     tau_c = 1e-10 (full accuracy) and at tau_c = 1e-6 (the mixed form's accuracy, for an
     equal-accuracy comparison).  A run counts its eigenpairs only if the count is exact
     and every eigenvalue is within 1e-10 ||A|| (tau_c 1e-10) or 1e-5 ||A|| (tau_c 1e-6).
-    Wall time runs from the resident start block to results on the host.
+    Wall time runs from the resident start block to results on the host.  As in the
+    paper's experiments (Section 4), every mode runs once per start-block seed 0..4 and
+    the averages are reported (after one untimed solve per workload).
     """
     from workloads import build_config, start_block
 
     out = {}
-    for name, reps in (("lap2d_64", 3), ("lap3d_pot_27", 1)):
+    for name in ("lap2d_64", "lap3d_pot_27"):
         A, (lmin, lmax), (a, b), cfg = build_config(name)
         exact = _window_fixture(name)
         normA = max(abs(lmin), abs(lmax))
         M = afsi.Matrix(A, device=0, bounds=(lmin, lmax))
-        X0 = start_block(A.n, cfg.p, seed=0)
-        rec_w = {"n": A.n, "p": cfg.p, "degree": cfg.degree, "eigenvalues": int(exact.size)}
+        X0s = {sd: start_block(A.n, cfg.p, seed=sd) for sd in seeds}
+        rec_w = {"n": A.n, "p": cfg.p, "degree": cfg.degree, "eigenvalues": int(exact.size),
+                 "seeds": list(seeds)}
         k1 = paper_initial_degree(lmin, lmax, a, b)
         rec_w["adaptive_k1_kmax"] = [k1, math.ceil(2.5 * k1)]
+
+        def solve(o, X0):
+            X = torch.from_numpy(X0).to(dev)
+            E = torch.zeros((A.n, cfg.p), dtype=torch.float64, device=dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, lam, res, r = afsi.afsi_solve(M.handle, a, b, o, X, E, cfg.p)
+            torch.cuda.synchronize()
+            return st, lam, res, r, time.perf_counter() - t0
+
         for label, form, tau_c, adaptive in SOLVE_MODES:
             o = afsi.afsi_options_default(math.ceil(2.5 * k1) if adaptive else cfg.degree)
             o.max_iter = 1500
@@ -614,26 +627,28 @@ def solve_rates(afsi, torch, dev):
             if adaptive:
                 o.adaptive = 1
                 o.damping = afsi.DAMP_LANCZOS
+            if label == SOLVE_MODES[0][0]:
+                solve(o, X0s[seeds[0]])  # untimed: first-use allocations
             tol = (1e-10 if tau_c <= 1e-10 else 1e-5) * normA
-            best = None
-            for rep in range(reps):
-                X = torch.from_numpy(X0).to(dev)
-                E = torch.zeros((A.n, cfg.p), dtype=torch.float64, device=dev)
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                st, lam, res, r = afsi.afsi_solve(M.handle, a, b, o, X, E, cfg.p)
-                torch.cuda.synchronize()
-                dt = time.perf_counter() - t0
+            runs = []
+            for sd in seeds:
+                st, lam, res, r, dt = solve(o, X0s[sd])
                 err = float(np.max(np.abs(lam - exact))) if lam.size == exact.size else None
                 good = int(lam.size) if (st == 0 and err is not None and err <= tol) else 0
-                rec = {"seconds": round(dt, 4), "eigenpairs": good, "iterations": r.iterations,
-                       "eigenpairs_per_s": round(good / dt, 2), "tau_c": tau_c,
-                       "max_abs_eig_err": err,
-                       "max_residual": float(np.max(res)) if res.size else None}
-                if best is None or rec["seconds"] < best["seconds"]:
-                    best = rec
-            rec_w[label] = best
-            log(f"solve {name} {label}: {best}")
+                runs.append({"seed": sd, "seconds": round(dt, 4), "eigenpairs": good,
+                             "iterations": r.iterations, "eigenpairs_per_s": round(good / dt, 2),
+                             "max_abs_eig_err": err,
+                             "max_residual": float(np.max(res)) if res.size else None})
+            rate = [x["eigenpairs_per_s"] for x in runs]
+            rec = {"eigenpairs_per_s": round(float(np.mean(rate)), 2),
+                   "eigenpairs_per_s_min_max": [min(rate), max(rate)],
+                   "seconds": round(float(np.mean([x["seconds"] for x in runs])), 4),
+                   "iterations": round(float(np.mean([x["iterations"] for x in runs])), 1),
+                   "all_correct": all(x["eigenpairs"] == exact.size for x in runs), "tau_c": tau_c,
+                   "max_abs_eig_err": max((x["max_abs_eig_err"] or 0.0) for x in runs),
+                   "max_residual": max((x["max_residual"] or 0.0) for x in runs)}
+            rec_w[label] = rec
+            log(f"solve {name} {label}: {rec}")
         for fast, slow in (("mixed", "fp64_tau1e-6"), ("mixed_adaptive", "fp64_adaptive_tau1e-6")):
             if rec_w[slow]["eigenpairs_per_s"] > 0:
                 rec_w[f"{fast}_vs_fp64_equal_accuracy"] = round(
