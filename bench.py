@@ -484,7 +484,9 @@ def batched_record(afsi, torch, dev, groups=16, cols=96, launches=30):
     """Batched slice filter: 16 spectrum slices x 96 columns of the 100^3 matrix advanced
     by one launch per step (A read once), against the same groups as 16 launches.
     `batched`: every group at the same step, so all read one source block;
-    `batched_mixed_sources`: odd groups one step ahead, so the launch mixes two sources.
+    `batched_mixed_sources`: odd groups one step ahead, so the launch mixes two sources;
+    `grouped*`: the same slices each in its own contiguous n x 96 blocks, advanced by one
+    grouped launch per step (or one launch per slice).
 
     Every group is in the steady part of its own filter (steps 2..), with its own
     slice coefficients; bytes per launch = A once + per group one pass over each block
@@ -544,7 +546,39 @@ def batched_record(afsi, torch, dev, groups=16, cols=96, launches=30):
         out[mode] = {"ms_per_step": round(ms / launches, 3),
                      "gbs": round(total / (ms * 1e-3) / 1e9, 1)}
     out["batched_speedup"] = round(out["one_launch_per_group"]["ms_per_step"] / out["batched"]["ms_per_step"], 3)
+    X0 = X.cpu()
     del X, P0, P1
+    torch.cuda.empty_cache()
+    # the same slices, each in its own contiguous n x 96 blocks (the serving pool's layout):
+    # one grouped launch per step, and one launch per slice
+    own = []
+    for g in range(groups):
+        Xg = X0[:, g * cols:(g + 1) * cols].contiguous().to(dev)
+        own.append((Xg, torch.zeros_like(Xg), torch.zeros_like(Xg)))
+    del X0
+    for mode in ("grouped", "grouped_mixed_sources", "grouped_one_launch_per_slice"):
+        steps = list(range(2, 2 + launches))
+        total = 0
+        for warm in (True, False):
+            ev[0].record()
+            for s in steps:
+                gs = step_groups(s, 1 if mode == "grouped_mixed_sources" else 0)
+                sl = [(gs[g], *own[g]) for g in range(groups)]
+                if mode != "grouped_one_launch_per_slice":
+                    afsi.afsi_clenshaw_step_grouped(M.handle, sl)
+                    total += bytes_of(gs, True)
+                else:
+                    for g in range(groups):
+                        afsi.afsi_clenshaw_step_grouped(M.handle, [sl[g]])
+                    total += sum(bytes_of([x], True) for x in gs)
+            ev[1].record()
+            torch.cuda.synchronize()
+            if warm:
+                total = 0
+        ms = ev[0].elapsed_time(ev[1])
+        out[mode] = {"ms_per_step": round(ms / launches, 3),
+                     "gbs": round(total / (ms * 1e-3) / 1e9, 1)}
+    del own
     M.close()
     torch.cuda.empty_cache()
     return out

@@ -202,6 +202,27 @@ int afsi_clenshaw_step_params(const double *coeffs, int degree, int step, double
 int afsi_clenshaw_step_batched(afsi_matrix_t A, int ngroups, const afsi_step_group *groups,
                                const afsi_block *X, afsi_block *P0, afsi_block *P1, void *stream);
 
+/*
+ * Grouped step for spectrum slices of one matrix that keep their blocks apart: one
+ * product of every active slice, each on its own n x step.ncols blocks X, P0, P1
+ * (row-major, leading dimension ld, device, `dtype` R64/R32 for a real A, C128/C64
+ * for a complex A).  step holds the product's parameters exactly as for
+ * afsi_clenshaw_step_batched (step.col0 is ignored).  The library launches one kernel
+ * per distinct width (at most 32 slices each) whose gathers read whole rows of one
+ * contiguous block, and gives every column the same bits as afsi_filter_block.  Rows
+ * and pointers must be 16-byte aligned; a slice's three blocks must not overlap each
+ * other or another slice's.  Any number of slices.  Errors: AFSI_E_INVALID.
+ */
+typedef struct {
+    afsi_step_group step;
+    const void *X;
+    void *P0, *P1;
+    int64_t ld;
+} afsi_slice_blocks;
+
+int afsi_clenshaw_step_grouped(afsi_matrix_t A, int ngroups, const afsi_slice_blocks *slices,
+                               int32_t dtype, void *stream);
+
 /* ------------------------------------------------------------------ dense steps (FP64) */
 
 /*
@@ -341,10 +362,11 @@ int afsi_solve(afsi_matrix_t A, double a, double b, const afsi_options *opts, af
 /*
  * Continuous-batching server for many solves on one device (spectrum slicing of
  * one matrix, Section 1, and independent matrices).  Requests are admitted when
- * their device footprint fits `hbm_budget_bytes`: a pool of three concatenated
- * n x cols FP64 blocks per (matrix, filter dtype) (three more in FP32 for the
- * mixed form) plus n x p for the request's eigenvectors.  All filtering requests
- * of a pool advance together, one batched Clenshaw product (A read once) per
+ * their device footprint fits `hbm_budget_bytes`: a pool of three n x cols FP64
+ * buffers per (matrix, filter dtype) (three more in FP32 for the mixed form), in
+ * which a request owns a contiguous n x w slot of each, plus n x p for the
+ * request's eigenvectors.  All filtering requests of a pool advance together, one
+ * grouped Clenshaw product (afsi_clenshaw_step_grouped, one launch per width) per
  * round; each pool runs on its own HIP stream and host thread, so independent
  * matrices overlap on the device.  A request's results do not depend on what
  * else is running.  Matrices must outlive the requests that use them.
@@ -365,7 +387,7 @@ typedef struct {
 typedef struct {
     int64_t bytes_in_use, budget;
     int64_t queued, running, done, pools;
-    int64_t batched_launches, batched_groups; /* groups / launches = slices per launch */
+    int64_t batched_launches, batched_groups; /* grouped rounds; slices per round = groups / launches */
     double now;                               /* server clock (s) */
 } afsi_server_stats;
 

@@ -42,6 +42,11 @@ class afsi_step_group(C.Structure):
                 ("sigma", C.c_double), ("tau", C.c_double), ("alpha", C.c_double)]
 
 
+class afsi_slice_blocks(C.Structure):
+    _fields_ = [("step", afsi_step_group), ("X", C.c_void_p), ("P0", C.c_void_p), ("P1", C.c_void_p),
+                ("ld", C.c_int64)]
+
+
 class afsi_options(C.Structure):
     _fields_ = [("kmax", C.c_int32), ("k_init", C.c_int32), ("adaptive", C.c_int32),
                 ("damping", C.c_int32), ("m_exp", C.c_double), ("tau_a", C.c_double),
@@ -91,6 +96,7 @@ _SIGS = {
     "afsi_spmm": (C.c_int, [_P, _BP, _BP, _P]),
     "afsi_clenshaw_step_params": (C.c_int, [_P, C.c_int, C.c_int, C.c_double, C.c_double, C.POINTER(afsi_step_group)]),
     "afsi_clenshaw_step_batched": (C.c_int, [_P, C.c_int, C.POINTER(afsi_step_group), _BP, _BP, _BP, _P]),
+    "afsi_clenshaw_step_grouped": (C.c_int, [_P, C.c_int, C.POINTER(afsi_slice_blocks), C.c_int32, _P]),
     "afsi_block_inner": (C.c_int, [_BP, _BP, _BP, _P]),
     "afsi_block_gemm": (C.c_int, [_BP, _BP, C.c_double, _BP, _P]),
     "afsi_orthonormalize": (C.c_int, [_BP, _BP, _BP, _P]),
@@ -284,6 +290,20 @@ def afsi_clenshaw_step_params(coeffs, degree: int, step: int, l1: float, l2: flo
 def afsi_clenshaw_step_batched(h, groups, X, P0, P1, stream=None):
     arr = (afsi_step_group * max(len(groups), 1))(*groups)
     _check(lib().afsi_clenshaw_step_batched(h, len(groups), arr, _bref(_blk(X)), _bref(_blk(P0)), _bref(_blk(P1)), _stream(stream)))
+
+
+def afsi_clenshaw_step_grouped(h, slices, stream=None):
+    """slices: list of (afsi_step_group, X, P0, P1) with torch blocks of one dtype, each
+    n x step.ncols (its own leading dimension)."""
+    arr = (afsi_slice_blocks * max(len(slices), 1))()
+    dt = R64
+    for i, (g, X, P0, P1) in enumerate(slices):
+        bx, b0, b1 = _blk(X), _blk(P0), _blk(P1)
+        if not (bx.ld == b0.ld == b1.ld and bx.dtype == b0.dtype == b1.dtype):
+            raise AfsiError(-1, "a slice's X, P0, P1 must share ld and dtype")
+        arr[i] = afsi_slice_blocks(g, bx.ptr, b0.ptr, b1.ptr, bx.ld)
+        dt = bx.dtype
+    _check(lib().afsi_clenshaw_step_grouped(h, len(slices), arr, dt, _stream(stream)))
 
 
 def afsi_block_inner(X, Y, G, stream=None):

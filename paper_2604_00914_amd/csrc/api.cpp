@@ -606,6 +606,15 @@ int afsi_clenshaw_step_params(const double *coeffs, int degree, int step, double
     });
 }
 
+int afsi_clenshaw_step_grouped(afsi_matrix_t A, int ngroups, const afsi_slice_blocks *slices,
+                               int32_t dtype, void *stream) {
+    return guarded([&] {
+        check_matrix(A);
+        DeviceGuard dg(A->device);
+        grouped_step(A, ngroups, slices, dtype, as_stream(stream));
+    });
+}
+
 int afsi_clenshaw_step_batched(afsi_matrix_t A, int ngroups, const afsi_step_group *groups,
                                const afsi_block *X, afsi_block *P0, afsi_block *P1, void *stream) {
     return guarded([&] {
@@ -675,6 +684,86 @@ void batched_step(afsi_matrix_t A, int ngroups, const afsi_step_group *groups, i
         }
         AFSI_HIP(hipGetLastError());
     }
+}
+
+void grouped_step(afsi_matrix_t A, int ngroups, const afsi_slice_blocks *slices, int dtype,
+                  hipStream_t s) {
+    AFSI_REQUIRE(ngroups >= 0 && (ngroups == 0 || slices != nullptr), "bad slice list");
+    AFSI_REQUIRE(dtype >= AFSI_R64 && dtype <= AFSI_C64, "unknown dtype %d", dtype);
+    const int eb = elem_bytes(dtype);
+    const int64_t n = A->n;
+    std::vector<int> act;
+    std::vector<std::pair<uintptr_t, uintptr_t>> spans;
+    for (int g = 0; g < ngroups; ++g) {
+        const afsi_slice_blocks &S = slices[g];
+        if (!S.step.active || S.step.ncols == 0) continue;
+        const afsi_step_group &G = S.step;
+        AFSI_REQUIRE(G.ncols > 0 && S.ld >= G.ncols, "slice %d: bad ncols / ld", g);
+        AFSI_REQUIRE(S.X && S.P0 && S.P1, "slice %d: NULL block", g);
+        AFSI_REQUIRE(G.src >= 0 && G.src <= 2 && (G.dst == 1 || G.dst == 2) && G.src != G.dst,
+                     "slice %d: bad src/dst", g);
+        const uintptr_t len = n == 0 ? 0 : (uintptr_t)(((n - 1) * S.ld + G.ncols) * eb);
+        for (const void *ptr : {S.X, (const void *)S.P0, (const void *)S.P1}) {
+            const uintptr_t a = (uintptr_t)ptr, b = a + len;
+            for (auto &o : spans)
+                AFSI_REQUIRE(b <= o.first || o.second <= a, "slice %d overlaps another block", g);
+            spans.push_back({a, b});
+        }
+        act.push_back(g);
+    }
+    if (act.empty() || n == 0) return;
+    const MatView mv = matrix_view(A, dtype, s);
+    // slices whose rows are whole 16-byte vectors go to the grouped kernel, by width
+    std::map<int, std::vector<int>> by_width;
+    std::vector<int> rest;
+    for (int g : act) {
+        const afsi_slice_blocks &S = slices[g];
+        const bool vec = (S.step.ncols * eb) % 16 == 0 && (S.ld * eb) % 16 == 0 &&
+                         aligned16(S.X) && aligned16(S.P0) && aligned16(S.P1);
+        if (vec && S.step.ncols * eb / 16 < (1 << 30)) by_width[(int)(S.step.ncols * eb / 16)].push_back(g);
+        else rest.push_back(g);
+    }
+    for (auto &kv : by_width) {
+        const int p16 = kv.first;
+        const std::vector<int> &gs = kv.second;
+        for (size_t g0 = 0; g0 < gs.size(); g0 += kGroupedMax) {
+            GroupArgs args;
+            std::memset(&args, 0, sizeof args);
+            const size_t cnt = std::min<size_t>(kGroupedMax, gs.size() - g0);
+            for (size_t k = 0; k < cnt; ++k) {
+                const afsi_slice_blocks &S = slices[gs[g0 + k]];
+                args.X[k] = S.X;
+                args.P0[k] = S.P0;
+                args.P1[k] = S.P1;
+                args.ldv[k] = S.ld * eb / 16;
+                args.src[k] = S.step.src;
+                args.dst[k] = S.step.dst;
+                args.has_v[k] = S.step.has_v;
+                args.sigma[k] = S.step.sigma;
+                args.tau[k] = S.step.tau;
+                args.alpha[k] = S.step.alpha;
+            }
+            args.ngroups = (int)cnt;
+            bool done = false;
+            switch (dtype) {
+            case AFSI_R64: done = clenshaw_r64_grouped(mv, p16, args, s); break;
+            case AFSI_R32: done = clenshaw_r32_grouped(mv, p16, args, s); break;
+            case AFSI_C128: done = clenshaw_c128_grouped(mv, p16, args, s); break;
+            case AFSI_C64: done = clenshaw_c64_grouped(mv, p16, args, s); break;
+            }
+            if (!done)
+                for (size_t k = 0; k < cnt; ++k) rest.push_back(gs[g0 + k]);
+        }
+    }
+    // widths without an exact lane mapping, and unaligned blocks: one product each
+    for (int g : rest) {
+        const afsi_slice_blocks &S = slices[g];
+        const void *src = S.step.src == 0 ? S.X : (S.step.src == 1 ? (const void *)S.P0 : S.P1);
+        void *dst = S.step.dst == 1 ? S.P0 : S.P1;
+        run_step(mv, dtype, src, S.X, dst, S.step.ncols, S.ld, S.step.has_v != 0,
+                 S.step.alpha != 0.0, S.step.sigma, S.step.tau, S.step.alpha, s);
+    }
+    AFSI_HIP(hipGetLastError());
 }
 
 void gather_cols(int dtype, const void *src, int64_t n, int64_t ld, const int32_t *cols,

@@ -143,6 +143,18 @@ struct BatchArgs {
     double sigma[64], tau[64], alpha[64];
 };
 
+// Grouped step: up to kGroupedMax slices with their own blocks, one launch.
+constexpr int kGroupedMax = 32;
+struct GroupArgs {
+    int ngroups;
+    int64_t npad;  // rows per slice rounded up to whole workgroups (set by the launcher)
+    const void *X[kGroupedMax];
+    void *P0[kGroupedMax], *P1[kGroupedMax];
+    int64_t ldv[kGroupedMax];  // leading dimension in 16-byte vectors
+    int src[kGroupedMax], dst[kGroupedMax], has_v[kGroupedMax];
+    double sigma[kGroupedMax], tau[kGroupedMax], alpha[kGroupedMax];
+};
+
 #define AFSI_DECLARE_STEP_ENTRY(NAME)                                                               \
     void NAME##_step(const MatView &A, const void *src, const void *X, void *dst, int p16,          \
                      int64_t ldv, bool hv, bool hx, double sg, double ta, double al,               \
@@ -150,7 +162,8 @@ struct BatchArgs {
     void NAME##_batched(const MatView &A, const void *X, void *P0, void *P1, int p16, int64_t ldv,  \
                         const BatchArgs &args, hipStream_t s);                                      \
     void NAME##_scalar(const MatView &A, const void *src, const void *X, void *dst, int p,          \
-                       int64_t ld, bool hv, bool hx, double sg, double ta, double al, hipStream_t s);
+                       int64_t ld, bool hv, bool hx, double sg, double ta, double al, hipStream_t s); \
+    bool NAME##_grouped(const MatView &A, int p16, GroupArgs &args, hipStream_t s);
 AFSI_DECLARE_STEP_ENTRY(clenshaw_r64)
 AFSI_DECLARE_STEP_ENTRY(clenshaw_r32)
 AFSI_DECLARE_STEP_ENTRY(clenshaw_c128)
@@ -221,6 +234,8 @@ void gather_cols(int dtype, const void *src, int64_t n, int64_t ld, const int32_
                  int64_t count, void *dst, int64_t ldd, hipStream_t s);
 void batched_step(afsi_matrix_t A, int ngroups, const afsi_step_group *groups, int dtype,
                   const void *X, void *P0, void *P1, int64_t ptot, int64_t ld, hipStream_t s);
+void grouped_step(afsi_matrix_t A, int ngroups, const afsi_slice_blocks *slices, int dtype,
+                  hipStream_t s);
 
 // ---------------------------------------------------------------- host linear algebra
 // host_cholesky_inverse, host_eigh: host_linalg.h (built without HIP, with OpenMP).

@@ -2,13 +2,16 @@
 //
 // Requests (matrix, interval, block width, options, seed) are admitted when their
 // device footprint fits a byte budget.  Admitted requests of the same matrix and
-// filter precision share a pool: three concatenated FP64 blocks (plus three in the
-// filter precision for the mixed form) whose column ranges are handed out to
-// requests, so the CSR matrix and every request's subspace stay resident.  Each
-// pool has its own HIP stream and host thread.  A pool thread repeats rounds:
-//   * one batched Clenshaw product (afsi_clenshaw_step_batched semantics) for every
-//     request that is filtering, whatever product index each one is at - the
-//     matrix is read once for all of them;
+// filter precision share a pool: three FP64 buffers (plus three in the filter
+// precision for the mixed form) of n x cap elements each, handed out in slots: a
+// request owning pool columns [c0, c0 + w) owns the contiguous n x w region at
+// element offset n * c0 of every buffer (row-major, leading dimension w), so the CSR
+// matrix and every request's subspace stay resident and every request's rows are
+// contiguous.  Each pool has its own HIP stream and host thread.  A pool thread
+// repeats rounds:
+//   * one grouped Clenshaw product (afsi_clenshaw_step_grouped semantics) for every
+//     request that is filtering, whatever product index each one is at - one launch
+//     per width for all of them;
 //   * the dense phases (Cholesky QR, Rayleigh-Ritz, residuals, locking - the steps
 //     of Algorithm 4) of every request whose filter just finished.
 // Requests that arrive while others run are admitted as soon as columns and bytes
@@ -64,9 +67,6 @@ struct Session {
     std::vector<double> coeffs;
     double l1 = 0, l2 = 0, tau_abs = 0;
     int k_cur = 1, step = 0, phase = PH_INIT;
-    // the filter's two product blocks exchanged (chosen when the filter starts, so that
-    // every filtering session reads its source from the same block in each launch)
-    int swap = 0;
     int64_t n_check_prev = 0;
     std::vector<int> degrees;
 };
@@ -84,7 +84,6 @@ struct Pool {
     std::vector<uint8_t> used;  // per column
     std::list<Session> sessions;
     std::deque<Session> incoming;
-    int64_t rounds = 0;  // batched rounds issued, each one step of every filtering session
     size_t bytes = 0;
     bool mixed() const { return fdt != dt; }
 };
@@ -240,6 +239,11 @@ void *col_ptr(void *base, int64_t col, int dt) {
     return (char *)base + (size_t)col * elem_bytes(dt);
 }
 
+// A session's n x s.cap region of one pool buffer (leading dimension s.cap).
+void *slot_ptr(const Pool *P, void *base, const Session &s, int dt) {
+    return (char *)base + (size_t)P->n * s.col0 * elem_bytes(dt);
+}
+
 void finish(Pool *P, Session &s, int status, const std::string &err) {
     Server *S = P->S;
     Request *r = s.r;
@@ -262,9 +266,9 @@ void finish(Pool *P, Session &s, int status, const std::string &err) {
 void init_session(Pool *P, Session &s) {
     Request *r = s.r;
     const int comp = is_complex(P->dt) ? 2 : 1;
-    void *B0 = col_ptr(P->B[0], s.col0, P->dt);
-    launch_fill_normal((double *)B0, P->n, r->p, P->cap, comp, r->seed, P->stream);
-    orthonormalize_dev(P->dt, B0, col_ptr(P->B[1], s.col0, P->dt), P->n, r->p, P->cap, P->stream,
+    void *B0 = slot_ptr(P, P->B[0], s, P->dt);
+    launch_fill_normal((double *)B0, P->n, r->p, s.cap, comp, r->seed, P->stream);
+    orthonormalize_dev(P->dt, B0, slot_ptr(P, P->B[1], s, P->dt), P->n, r->p, s.cap, P->stream,
                        nullptr);
     s.coeffs.resize(r->opts.kmax + 1);
     filter_coefficients(r->A->lmin, r->A->lmax, r->a, r->b, r->opts.kmax, r->opts.damping,
@@ -288,8 +292,8 @@ void start_filter(Pool *P, Session &s) {
     s.phase = PH_FILTER;
     s.step = 0;
     if (P->mixed()) {
-        afsi_block src{col_ptr(P->B[0], s.col0, P->dt), P->n, s.p_act, P->cap, P->dt};
-        afsi_block dst{col_ptr(P->F[0], s.col0, P->fdt), P->n, s.p_act, P->cap, P->fdt};
+        afsi_block src{slot_ptr(P, P->B[0], s, P->dt), P->n, s.p_act, s.cap, P->dt};
+        afsi_block dst{slot_ptr(P, P->F[0], s, P->fdt), P->n, s.p_act, s.cap, P->fdt};
         launch_convert(src, dst, P->stream);
     }
 }
@@ -309,21 +313,20 @@ void publish(Pool *P, Request *r, int iterations, int64_t spmv, int64_t locked) 
 int dense_phase(Pool *P, Session &s) {
     Request *r = s.r;
     const int dt = P->dt;
-    const int64_t n = P->n, ld = P->cap, pa = s.p_act;
-    // the last product's output block: 1 + (k-1) % 2, or the other one when swapped
-    const int outi = s.swap ? 2 - (s.k_cur - 1) % 2 : 1 + (s.k_cur - 1) % 2;
+    const int64_t n = P->n, ld = s.cap, pa = s.p_act;
+    const int outi = 1 + (s.k_cur - 1) % 2;  // product output lands in P[(k-1) % 2]
     void *q, *w;
     if (P->mixed()) {
-        afsi_block src{col_ptr(P->F[outi], s.col0, P->fdt), n, pa, ld, P->fdt};
-        afsi_block dst{col_ptr(P->B[1], s.col0, dt), n, pa, ld, dt};
+        afsi_block src{slot_ptr(P, P->F[outi], s, P->fdt), n, pa, ld, P->fdt};
+        afsi_block dst{slot_ptr(P, P->B[1], s, dt), n, pa, ld, dt};
         launch_convert(src, dst, P->stream);
-        q = col_ptr(P->B[1], s.col0, dt);
-        w = col_ptr(P->B[2], s.col0, dt);
+        q = slot_ptr(P, P->B[1], s, dt);
+        w = slot_ptr(P, P->B[2], s, dt);
     } else {
-        q = col_ptr(P->B[outi], s.col0, dt);
-        w = col_ptr(P->B[3 - outi], s.col0, dt);
+        q = slot_ptr(P, P->B[outi], s, dt);
+        w = slot_ptr(P, P->B[3 - outi], s, dt);
     }
-    void *v = col_ptr(P->B[0], s.col0, dt);
+    void *v = slot_ptr(P, P->B[0], s, dt);
     s.degrees.push_back(s.k_cur);
     publish(P, r, 1, (int64_t)s.k_cur * pa, 0);
     if (r->n_lock > 0) project_out_dev(dt, r->evecs, r->p, r->n_lock, q, ld, n, pa, P->stream);
@@ -409,7 +412,7 @@ void release_pool(Pool *P) {
 void pool_thread(Pool *P) {
     Server *S = P->S;
     (void)hipSetDevice(S->device);
-    std::vector<afsi_step_group> groups;
+    std::vector<afsi_slice_blocks> groups;
     std::vector<Session *> filt;
     for (;;) {
         {
@@ -454,31 +457,25 @@ void pool_thread(Pool *P) {
         groups.clear();
         for (auto &s : P->sessions)
             if (s.phase == PH_FILTER) {
-                afsi_step_group g{};
-                step_params(s.coeffs.data(), s.k_cur, s.step, s.l1, s.l2, &g);
-                // step s >= 1 reads block 1 + (s-1) % 2; a filter starting in an even round
-                // exchanges the two blocks, so that every filter past its first step reads
-                // block 1 + rounds % 2 and the batched product gathers from one block
-                if (s.step == 0) s.swap = P->rounds % 2 == 0;
-                if (s.swap) {
-                    if (g.src != 0) g.src = 3 - g.src;
-                    g.dst = 3 - g.dst;
-                }
-                g.col0 = s.col0;
-                g.ncols = round_up(s.p_act, P->E);
-                g.active = 1;
+                afsi_slice_blocks g{};
+                step_params(s.coeffs.data(), s.k_cur, s.step, s.l1, s.l2, &g.step);
+                g.step.col0 = 0;
+                g.step.ncols = round_up(s.p_act, P->E);
+                g.step.active = 1;
+                void **buf = P->mixed() ? P->F : P->B;
+                g.X = slot_ptr(P, buf[0], s, P->fdt);
+                g.P0 = slot_ptr(P, buf[1], s, P->fdt);
+                g.P1 = slot_ptr(P, buf[2], s, P->fdt);
+                g.ld = s.cap;
                 groups.push_back(g);
                 filt.push_back(&s);
             }
         try {
-            for (size_t g0 = 0; g0 < groups.size(); g0 += 64) {
-                const int ng = (int)std::min<size_t>(64, groups.size() - g0);
-                void **buf = P->mixed() ? P->F : P->B;
-                batched_step(P->A, ng, groups.data() + g0, P->fdt, buf[0], buf[1], buf[2], P->cap,
-                             P->cap, P->stream);
+            if (!groups.empty()) {
+                grouped_step(P->A, (int)groups.size(), groups.data(), P->fdt, P->stream);
                 std::lock_guard<std::mutex> lk(S->mu);
                 ++S->launches;
-                S->launch_groups += ng;
+                S->launch_groups += (int64_t)groups.size();
             }
         } catch (const Error &e) {
             const std::string msg = afsi_last_error();
@@ -490,7 +487,6 @@ void pool_thread(Pool *P) {
             P->sessions.remove_if([](const Session &s) { return s.phase == -1; });
             continue;
         }
-        if (!groups.empty()) ++P->rounds;
         for (auto *s : filt)
             if (++s->step == s->k_cur) s->phase = PH_DENSE;
         for (auto it = P->sessions.begin(); it != P->sessions.end(); ++it) {

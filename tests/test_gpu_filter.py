@@ -324,3 +324,77 @@ def test_full_size_batched_slices_sampled_columns(stagger):
     for j, g in enumerate(range(G)):
         ref = clenshaw_filter(A, np.ascontiguousarray(X0[:, pick[j]:pick[j] + 1]), coeffs[g], l1, l2)
         _check(got[:, j:j + 1], ref, F64_TOL)
+
+
+# (ncols, ld, degree, interval, first step): widths with an exact lane mapping (the
+# grouped kernel, two slices share a launch), a padded leading dimension, and widths
+# that fall back to one product per slice (10 columns: no exact mapping; 3 columns: not
+# whole 16-byte vectors)
+GROUPED = [(32, 32, 7, (3.0, 3.5), 0), (96, 104, 12, (5.0, 5.3), 1), (32, 32, 5, (9.0, 11.0), 2),
+           (64, 64, 8, (7.0, 7.4), 1), (128, 136, 9, (2.0, 2.4), 2), (10, 10, 6, (4.0, 4.6), 0),
+           (3, 4, 4, (6.0, 6.2), 1)]
+
+
+@pytest.mark.parametrize("cplx,single", [(False, False), (False, True), (True, False), (True, True)])
+def test_grouped_slices_bitwise_equal_to_single_filters(cplx, single):
+    t = torch()
+    if cplx:
+        A = tight_binding_3d_periodic(8, seed=3)
+        lmin, lmax = -7.5, 7.5
+        groups = [(nc, ld, k, (iv[0] - 5.0, iv[1] - 5.0), st) for nc, ld, k, iv, st in GROUPED]
+    else:
+        A = laplacian_3d_dirichlet(10, 2.0, seed=4)
+        lmin, lmax = 0.0, 14.0
+        groups = GROUPED
+    l1, l2 = co.affine_map(lmin, lmax)
+    dt = _tdt(cplx, single)
+    M = afsi.Matrix(A, bounds=(lmin, lmax))
+    blocks, storage, X0s, coeffs = [], [], [], []
+    for g, (nc, ld, k, iv, st) in enumerate(groups):
+        X0 = start_block(A.n, nc, seed=20 + g, complex_=cplx)
+        X0s.append(X0)
+        coeffs.append(afsi.afsi_filter_coefficients(lmin, lmax, iv[0], iv[1], k, "jackson"))
+        bufs = [t.zeros((A.n, ld), dtype=dt, device=DEV) for _ in range(3)]
+        bufs[0][:, :nc] = t.from_numpy(X0).to(DEV).to(dt)
+        storage.append(bufs)
+        blocks.append([b[:, :nc] for b in bufs])
+    total = max(st + k for (nc, ld, k, iv, st) in groups)
+    for step in range(total):
+        sl = []
+        for g, (nc, ld, k, iv, st) in enumerate(groups):
+            s = step - st
+            if 0 <= s < k:
+                sl.append((afsi.afsi_clenshaw_step_params(coeffs[g], k, s, l1, l2, ncols=nc), *blocks[g]))
+        afsi.afsi_clenshaw_step_grouped(M.handle, sl)
+    t.cuda.synchronize()
+    for g, (nc, ld, k, iv, st) in enumerate(groups):
+        X, P0, P1 = blocks[g]
+        Yg = (P0 if (k - 1) % 2 == 0 else P1).cpu().numpy()
+        Xs = t.from_numpy(X0s[g]).to(DEV).to(dt)
+        Ys, Ws = t.empty_like(Xs), t.empty_like(Xs)
+        afsi.afsi_filter_block(M.handle, coeffs[g], k, Xs, Ys, Ws)
+        t.cuda.synchronize()
+        assert np.array_equal(Yg, Ys.cpu().numpy()), g
+        ref = oracle_filter(A, X0s[g], lmin, lmax, iv[0], iv[1], k)
+        _check(Yg.astype(np.complex128 if cplx else np.float64), ref, f32_tol(k) if single else F64_TOL)
+        # the padding columns of the slice's storage are never written
+        for b in storage[g][1:]:
+            assert not b[:, nc:].cpu().numpy().any()
+    M.close()
+
+
+def test_grouped_rejects_overlapping_slices():
+    t = torch()
+    A = laplacian_3d_dirichlet(6, 1.0, seed=2)
+    M = afsi.Matrix(A, bounds=(0.0, 14.0))
+    c = afsi.afsi_filter_coefficients(0.0, 14.0, 3.0, 4.0, 5)
+    l1, l2 = co.affine_map(0.0, 14.0)
+    X = to_dev(start_block(A.n, 32, seed=1))
+    P = t.zeros((A.n, 64), dtype=t.float64, device=DEV)
+    g = afsi.afsi_clenshaw_step_params(c, 5, 2, l1, l2, ncols=32)
+    with pytest.raises(afsi.AfsiError):  # P0 and P1 of one slice overlap
+        afsi.afsi_clenshaw_step_grouped(M.handle, [(g, X, P[:, :32], P[:, 16:48])])
+    Q0, Q1 = t.zeros_like(X), t.zeros_like(X)
+    with pytest.raises(afsi.AfsiError):  # two slices share a block
+        afsi.afsi_clenshaw_step_grouped(M.handle, [(g, X, Q0, Q1), (g, X, t.zeros_like(X), t.zeros_like(X))])
+    M.close()
