@@ -88,6 +88,9 @@ def main():
     ap.add_argument("--sweep", default=None, metavar="OUT",
                     help="only measure the filter alone on every workload and precision; "
                          "one JSON line per case into OUT")
+    ap.add_argument("--slices", default=None, metavar="OUT",
+                    help="only measure the slice steps (16 slices x 96 columns of the 100^3 matrix: "
+                         "side by side in one block, and each in its own block); one JSON line into OUT")
     ap.add_argument("--sensitivity", default=None, metavar="OUT",
                     help="only run the parameter-sensitivity solves (damping exponent m, "
                          "tau_a, C_r adaptive vs fixed); one JSON line per solve into OUT")
@@ -121,6 +124,12 @@ def main():
         return
     if args.sensitivity:
         sensitivity(afsi, torch, dev, args.sensitivity)
+        return
+    if args.slices:
+        rec = batched_record(afsi, torch, dev)
+        log(f"slices: {rec}")
+        with open(args.slices, "w") as fh:
+            fh.write(json.dumps(rec) + "\n")
         return
 
     t0 = time.time()
