@@ -3,8 +3,8 @@
 //
 //  * host_cholesky_inverse: R^{-1} for the Cholesky factor R^H R = G + shift I, with
 //    symmetric diagonal scaling (G -> D G D, unit diagonal) before factoring; used by
-//    Cholesky QR, where only X R^{-1} is needed.  Right-looking factorisation and a
-//    row-oriented inverse: every inner loop is a contiguous axpy.
+//    Cholesky QR, where only X R^{-1} is needed.  Right-looking factorisation in
+//    panels and a row-block inverse, both with register-tiled updates.
 //  * host_eigh: Hermitian eigendecomposition B = U diag(w) U^H (Golub & Van Loan,
 //    Matrix Computations, ch. 8.3): Householder reduction to tridiagonal form
 //    (complex reflectors for Hermitian B), a diagonal unitary scaling that makes the
@@ -93,6 +93,52 @@ static inline T dot_lanes(const T *a, const T *b, int64_t m) {
     return acc[0];
 }
 
+// C[r][c] -= sum_{k<kb} op(A)[r][k] * B[k][c] on an RB x CB register tile:
+// op(A)[r][k] = conj(A[k * lda + r]) (TRANS_A, the panel of the Cholesky update) or
+// A[r * lda + k].  Full tiles only; the caller masks what it stores.
+constexpr int kRB = 4, kCB = 8;
+template <class T, bool TRANS_A>
+static inline void tile_product(int64_t kb, const T *A, int64_t lda, const T *B, int64_t ldb,
+                                T (&acc)[kRB][kCB]) {
+    for (int r = 0; r < kRB; ++r)
+        for (int c = 0; c < kCB; ++c) acc[r][c] = T(0);
+    for (int64_t k = 0; k < kb; ++k) {
+        T f[kRB], v[kCB];
+        for (int r = 0; r < kRB; ++r) f[r] = TRANS_A ? conjv(A[k * lda + r]) : A[r * lda + k];
+        const T *bk = B + k * ldb;
+        for (int c = 0; c < kCB; ++c) v[c] = bk[c];
+        for (int r = 0; r < kRB; ++r)
+            for (int c = 0; c < kCB; ++c) acc[r][c] += f[r] * v[c];
+    }
+}
+
+// Upper part of H (m x m, ldh) -= P^H P for the kb x m panel P (ldp): H[i][l] for l >= i.
+// Rows and columns are processed in register tiles; P is padded by the caller to a whole
+// number of tiles in both directions (zero columns), so tiles never read past it.
+template <class T>
+static void update_upper(int64_t m, int64_t kb, const T *P, int64_t ldp, T *H, int64_t ldh) {
+    for (int64_t i0 = 0; i0 < m; i0 += kRB)
+        for (int64_t l0 = i0 / kCB * kCB; l0 < m; l0 += kCB) {
+            T acc[kRB][kCB];
+            tile_product<T, true>(kb, P + i0, ldp, P + l0, ldp, acc);
+            for (int r = 0; r < kRB && i0 + r < m; ++r) {
+                T *hr = H + (i0 + r) * ldh;
+                for (int c = 0; c < kCB && l0 + c < m; ++c)
+                    if (l0 + c >= i0 + r) hr[l0 + c] -= acc[r][c];
+            }
+        }
+}
+
+// Cholesky QR's host factor: R^{-1} with R^H R = G + shift I (upper R), computed on the
+// unit-diagonal scaling H' = D (G + shift I) D, D = diag(1/sqrt(G_ii + shift)).
+// Factorisation: right-looking in panels of kPanel rows, each panel finished row by row
+// and then subtracted from the trailing rows as one register-tiled update (the trailing
+// matrix is read once per panel instead of once per row).  Inverse: Z = R'^{-1} by row
+// blocks from the bottom, each block's contribution of the rows below as one tiled
+// product.  R = R' D^{-1}, so R^{-1} = D R'^{-1}.  Single-threaded: on the 16-core host
+// of the GPU machine p = 360 takes 0.56 ms on one thread and 0.68 ms on sixteen (the
+// row-by-row version took 1.62 ms).
+static const int64_t kPanel = 32;
 template <class T>
 static bool chol_inv_impl(int64_t p, T *G, int64_t ld, double shift) {
     std::vector<double> dscale(p);
@@ -101,47 +147,74 @@ static bool chol_inv_impl(int64_t p, T *G, int64_t ld, double shift) {
         if (!(h > 0.0) || !std::isfinite(h)) return false;
         dscale[i] = 1.0 / std::sqrt(h);
     }
-    // H' = D (G + shift I) D, upper triangle, row-major p x p
-    std::vector<T> R((size_t)p * p, T(0));
+    // work matrices padded to whole register tiles (pad columns and rows stay zero)
+    const int64_t pp = (p + kCB - 1) / kCB * kCB + kCB;
+    const int64_t pr = pp + kRB;
+    // H' = D (G + shift I) D, upper triangle, row-major p x p (ld pp)
+    std::vector<T> R((size_t)pr * pp, T(0));
     for (int64_t i = 0; i < p; ++i)
         for (int64_t j = i; j < p; ++j) {
             T h = G[i * ld + j];
             if (i == j) h = T(realv(h) + shift);
-            R[i * p + j] = h * (dscale[i] * dscale[j]);
+            R[i * pp + j] = h * (dscale[i] * dscale[j]);
         }
-    // right-looking upper Cholesky: finish row j, subtract its outer product from the
-    // trailing rows (upper part only)
-    for (int64_t j = 0; j < p; ++j) {
-        T *rj = &R[j * p];
-        const double d = realv(rj[j]);
-        if (!(d > 0.0) || !std::isfinite(d)) return false;
-        const double rjj = std::sqrt(d);
-        rj[j] = T(rjj);
-        const double inv = 1.0 / rjj;
-        for (int64_t l = j + 1; l < p; ++l) rj[l] *= inv;
-        for (int64_t i = j + 1; i < p; ++i) {
-            const T f = conjv(rj[i]);
-            T *ri = &R[i * p];
-            for (int64_t l = i; l < p; ++l) ri[l] -= f * rj[l];
+    for (int64_t k0 = 0; k0 < p; k0 += kPanel) {
+        const int64_t k1 = std::min(p, k0 + kPanel);
+        // finish rows k0..k1-1: scale row j, subtract it from the later rows of the panel
+        for (int64_t j = k0; j < k1; ++j) {
+            T *rj = &R[j * pp];
+            const double d = realv(rj[j]);
+            if (!(d > 0.0) || !std::isfinite(d)) return false;
+            const double rjj = std::sqrt(d);
+            rj[j] = T(rjj);
+            const double inv = 1.0 / rjj;
+            for (int64_t l = j + 1; l < p; ++l) rj[l] *= inv;
+            for (int64_t i = j + 1; i < k1; ++i) {
+                const T f = conjv(rj[i]);
+                T *ri = &R[i * pp];
+                for (int64_t l = i; l < p; ++l) ri[l] -= f * rj[l];
+            }
         }
+        // trailing rows k1..p-1 minus the panel's contribution
+        if (k1 < p) update_upper<T>(p - k1, k1 - k0, &R[k0 * pp + k1], pp, &R[k1 * pp + k1], pp);
     }
-    // Z = R^{-1} row by row from the bottom: Z[i, :] = -(sum_{k>i} R[i, k] Z[k, :]) / R_ii
-    std::vector<T> Z((size_t)p * p, T(0));
-    for (int64_t i = p - 1; i >= 0; --i) {
-        T *zi = &Z[i * p];
-        const T *ri = &R[i * p];
-        for (int64_t k = i + 1; k < p; ++k) {
-            const T f = ri[k];
-            const T *zk = &Z[k * p];
-            for (int64_t j = k; j < p; ++j) zi[j] += f * zk[j];
+    // Z = R'^{-1} (upper), by row blocks from the bottom:
+    //   Z[i, :] = (e_i - sum_{k > i} R'[i, k] Z[k, :]) / R'_ii
+    std::vector<T> Z((size_t)pr * pp, T(0));
+    for (int64_t i1 = p; i1 > 0;) {
+        const int64_t i0 = std::max<int64_t>(0, i1 - kPanel);
+        // rows below the block: Z[i, j] -= sum_{k >= i1} R'[i, k] Z[k, j] for j >= i1, as
+        // tiles of kRB rows (rows past the block compute into a scratch tile and are dropped)
+        if (i1 < p) {
+            const int64_t jt0 = i1 / kCB * kCB;
+            for (int64_t r0 = i0; r0 < i1; r0 += kRB)
+                for (int64_t j0 = jt0; j0 < p; j0 += kCB) {
+                    T acc[kRB][kCB];
+                    // k runs over i1 .. min(p, j0 + kCB): Z[k][j] = 0 for j < k
+                    const int64_t kend = std::min(p, j0 + kCB);
+                    tile_product<T, false>(kend - i1, &R[r0 * pp + i1], pp, &Z[i1 * pp + j0], pp, acc);
+                    for (int r = 0; r < kRB && r0 + r < i1; ++r)
+                        for (int c = 0; c < kCB && j0 + c < p; ++c)
+                            if (j0 + c >= i1) Z[(r0 + r) * pp + j0 + c] -= acc[r][c];
+                }
         }
-        const T inv = T(1.0) / ri[i];
-        for (int64_t j = i + 1; j < p; ++j) zi[j] *= -inv;
-        zi[i] = inv;
+        // inside the block, bottom row first
+        for (int64_t i = i1 - 1; i >= i0; --i) {
+            T *zi = &Z[i * pp];
+            const T *ri = &R[i * pp];
+            for (int64_t k = i + 1; k < i1; ++k) {
+                const T f = ri[k];
+                const T *zk = &Z[k * pp];
+                for (int64_t j = k; j < p; ++j) zi[j] -= f * zk[j];
+            }
+            const T inv = T(1.0) / ri[i];
+            for (int64_t j = i + 1; j < p; ++j) zi[j] *= inv;
+            zi[i] = inv;
+        }
+        i1 = i0;
     }
-    // R = R' D^{-1} with R'^H R' = H', so R^{-1} = D R'^{-1}
     for (int64_t i = 0; i < p; ++i)
-        for (int64_t j = 0; j < p; ++j) G[i * ld + j] = j >= i ? Z[i * p + j] * dscale[i] : T(0);
+        for (int64_t j = 0; j < p; ++j) G[i * ld + j] = j >= i ? Z[i * pp + j] * dscale[i] : T(0);
     return true;
 }
 

@@ -85,12 +85,84 @@ struct Pool {
     std::list<Session> sessions;
     std::deque<Session> incoming;
     size_t bytes = 0;
+    size_t blk = 0, fblk = 0;  // bytes of each FP64 / filter-precision buffer
     bool mixed() const { return fdt != dt; }
+};
+
+// Device memory of a server: chunks obtained with hipMalloc as needed and returned only
+// when the server is destroyed; pool buffers and eigenvector blocks are carved out of
+// them first-fit and given back (with coalescing) when their request or pool ends.
+// hipMalloc / hipFree of multi-GB buffers during a stream took seconds at times and
+// hipFree waits for the whole device, so the stream itself never calls them.
+struct Arena {
+    static constexpr size_t kAlign = 4096;
+    static constexpr size_t kChunkMin = size_t(8) << 30;
+    struct Chunk {
+        char *base = nullptr;
+        size_t size = 0;
+        std::map<size_t, size_t> free;  // offset -> length, disjoint and not adjacent
+    };
+    std::vector<Chunk> chunks;
+
+    // caller holds the server lock; throws on a failed hipMalloc
+    void *alloc(size_t bytes) {
+        bytes = std::max<size_t>((bytes + kAlign - 1) / kAlign * kAlign, kAlign);
+        for (auto &c : chunks)
+            for (auto it = c.free.begin(); it != c.free.end(); ++it)
+                if (it->second >= bytes) {
+                    const size_t off = it->first, len = it->second;
+                    c.free.erase(it);
+                    if (len > bytes) c.free[off + bytes] = len - bytes;
+                    return c.base + off;
+                }
+        Chunk c;
+        c.size = std::max(bytes, kChunkMin);
+        void *p = nullptr;
+        if (hipMalloc(&p, c.size) != hipSuccess) {
+            (void)hipGetLastError();
+            c.size = bytes;  // the rest of the device may still hold exactly this block
+            AFSI_HIP(hipMalloc(&p, c.size));
+        }
+        c.base = static_cast<char *>(p);
+        if (c.size > bytes) c.free[bytes] = c.size - bytes;
+        chunks.push_back(std::move(c));
+        return p;
+    }
+    // caller holds the server lock, and no work that uses the block is still queued
+    void release(void *p, size_t bytes) {
+        if (!p) return;
+        bytes = std::max<size_t>((bytes + kAlign - 1) / kAlign * kAlign, kAlign);
+        for (auto &c : chunks) {
+            char *q = static_cast<char *>(p);
+            if (q < c.base || q >= c.base + c.size) continue;
+            size_t off = (size_t)(q - c.base), len = bytes;
+            auto next = c.free.lower_bound(off);
+            if (next != c.free.end() && off + len == next->first) {
+                len += next->second;
+                next = c.free.erase(next);
+            }
+            if (next != c.free.begin()) {
+                auto prev = std::prev(next);
+                if (prev->first + prev->second == off) {
+                    off = prev->first;
+                    len += prev->second;
+                    c.free.erase(prev);
+                }
+            }
+            c.free[off] = len;
+            return;
+        }
+    }
+    void destroy() {
+        for (auto &c : chunks) (void)hipFree(c.base);
+        chunks.clear();
+    }
 };
 
 struct Server {
     int device = 0;
     int64_t budget = 0, in_use = 0;
+    Arena arena;
     std::mutex mu;
     std::condition_variable cv;     // request completions / thread exits
     std::deque<Request *> queue;
@@ -183,18 +255,17 @@ void try_admit(Server *S) {
             np->cap = cap;
             np->E = E;
             np->used.assign(cap, 0);
+            np->blk = (size_t)np->n * cap * elem_bytes(r->dt);
+            np->fblk = np->mixed() ? (size_t)np->n * cap * elem_bytes(r->fdt) : 0;
             try {
                 DeviceGuard dg(S->device);
-                const size_t blk = (size_t)np->n * cap * elem_bytes(r->dt);
-                for (auto &b : np->B) AFSI_HIP(hipMalloc(&b, std::max<size_t>(blk, 16)));
-                if (np->mixed()) {
-                    const size_t fb = (size_t)np->n * cap * elem_bytes(r->fdt);
-                    for (auto &b : np->F) AFSI_HIP(hipMalloc(&b, std::max<size_t>(fb, 16)));
-                }
+                for (auto &b : np->B) b = S->arena.alloc(np->blk);
+                if (np->mixed())
+                    for (auto &b : np->F) b = S->arena.alloc(np->fblk);
                 AFSI_HIP(hipStreamCreateWithFlags(&np->stream, hipStreamNonBlocking));
             } catch (...) {
-                for (auto b : np->B) (void)hipFree(b);
-                for (auto b : np->F) (void)hipFree(b);
+                for (auto &b : np->B) S->arena.release(b, np->blk), b = nullptr;
+                for (auto &b : np->F) S->arena.release(b, np->fblk), b = nullptr;
                 fail_queued(S, r, AFSI_E_NOMEM, "device allocation of the request's pool failed");
                 it = S->queue.erase(it);
                 continue;
@@ -213,7 +284,7 @@ void try_admit(Server *S) {
         }
         try {
             DeviceGuard dg(S->device);
-            AFSI_HIP(hipMalloc(&r->evecs, std::max<size_t>(r->evec_bytes, 16)));
+            r->evecs = S->arena.alloc(r->evec_bytes);
         } catch (...) {
             r->evecs = nullptr;
             fail_queued(S, r, AFSI_E_NOMEM, "device allocation of the eigenvector block failed");
@@ -378,7 +449,7 @@ int dense_phase(Pool *P, Session &s) {
     return DP_CONTINUE;
 }
 
-void sort_results(Pool *P, Request *r) {
+void sort_results(Pool *P, const Session &s, Request *r) {
     if (r->n_lock < 2) return;
     std::vector<int32_t> order(r->n_lock);
     std::iota(order.begin(), order.end(), 0);
@@ -387,25 +458,21 @@ void sort_results(Pool *P, Request *r) {
     for (int64_t t = 0; t < r->n_lock; ++t) lam[t] = r->lam[order[t]], res[t] = r->res[order[t]];
     r->lam = lam;
     r->res = res;
-    // permute the eigenvector columns through the pool's work block
+    // permute the eigenvector columns through the request's slot of the pool's work
+    // buffer (n x s.cap, free once the dense phase is over; n_lock <= p <= s.cap)
     const int dt = P->dt, eb = elem_bytes(dt);
-    void *tmp = nullptr;
-    AFSI_HIP(hipMalloc(&tmp, (size_t)P->n * r->n_lock * eb));
-    gather_cols(dt, r->evecs, P->n, r->p, order.data(), r->n_lock, tmp, r->n_lock, P->stream);
-    AFSI_HIP(hipMemcpy2DAsync(r->evecs, r->p * eb, tmp, r->n_lock * eb, r->n_lock * eb, P->n,
+    void *tmp = slot_ptr(P, P->B[2], s, dt);
+    gather_cols(dt, r->evecs, P->n, r->p, order.data(), r->n_lock, tmp, s.cap, P->stream);
+    AFSI_HIP(hipMemcpy2DAsync(r->evecs, r->p * eb, tmp, s.cap * eb, r->n_lock * eb, P->n,
                               hipMemcpyDeviceToDevice, P->stream));
     AFSI_HIP(hipStreamSynchronize(P->stream));
-    (void)hipFree(tmp);
 }
 
-void release_pool(Pool *P) {
-    // caller holds S->mu; the pool has no sessions
-    Server *S = P->S;
-    S->pools.erase(std::make_pair(P->A, P->fdt));
-    S->in_use -= (int64_t)P->bytes;
+// Stream of a pool that has left S->pools (so no request can be admitted to it): wait
+// for its work, then destroy it.  Called without S->mu; afterwards, under the lock, the
+// caller gives the pool's buffers back to the arena.
+void retire_pool_stream(Pool *P) {
     (void)hipStreamSynchronize(P->stream);
-    for (auto b : P->B) (void)hipFree(b);
-    for (auto b : P->F) (void)hipFree(b);
     (void)hipStreamDestroy(P->stream);
 }
 
@@ -427,7 +494,13 @@ void pool_thread(Pool *P) {
                     s.r->status = AFSI_E_INVALID;
                     s.r->error = "server stopped";
                 }
-                release_pool(P);
+                S->pools.erase(std::make_pair(P->A, P->fdt));
+                lk.unlock();
+                retire_pool_stream(P);
+                lk.lock();
+                for (auto b : P->B) S->arena.release(b, P->blk);
+                for (auto b : P->F) S->arena.release(b, P->fblk);
+                S->in_use -= (int64_t)P->bytes;
                 --S->live_threads;
                 try_admit(S);
                 S->cv.notify_all();
@@ -494,7 +567,7 @@ void pool_thread(Pool *P) {
             try {
                 const int outcome = dense_phase(P, *it);
                 if (outcome != DP_CONTINUE) {
-                    sort_results(P, it->r);
+                    sort_results(P, *it, it->r);
                     finish(P, *it, outcome == DP_CONVERGED ? AFSI_OK : AFSI_E_NOCONV, "");
                     done.push_back(it);
                 }
@@ -540,8 +613,8 @@ int afsi_server_destroy(afsi_server_t S) {
         S->queue.clear();
         S->cv.wait(lk, [&] { return S->live_threads == 0; });
         DeviceGuard dg(S->device);
-        for (auto &kv : S->reqs)
-            if (kv.second->evecs) (void)hipFree(kv.second->evecs);
+        (void)hipDeviceSynchronize();
+        S->arena.destroy();  // every pool and eigenvector block lives in it
         lk.unlock();
         delete S;
     });
@@ -676,9 +749,12 @@ int afsi_server_fetch(afsi_server_t S, int64_t id, double *eigenvalues, double *
                                       r->A->n, hipMemcpyDeviceToDevice, s));
             AFSI_HIP(hipStreamSynchronize(s));
         }
+        // the pool thread synchronised its stream after the last write to evecs, and the
+        // copy above is complete: the block can go back to the arena
         std::lock_guard<std::mutex> lk(S->mu);
         if (r->evecs) {
-            (void)hipFree(r->evecs);
+            S->arena.release(r->evecs, r->evec_bytes);
+            r->evecs = nullptr;
             S->in_use -= (int64_t)r->evec_bytes;
         }
         try_admit(S);
