@@ -59,15 +59,19 @@ __global__ __launch_bounds__(256, 4) void clenshaw_batched_kernel(
 #pragma unroll
     for (int v = 0; v < VN; ++v) acc[v] = Tr::zero();
     for (int e0 = start; e0 < end; e0 += U) {
+        // the tail gathers the clamped entry with a zero coefficient, so that nothing
+        // in the chunk is conditional and every gather is issued before the first
+        // wait (16 slices x 96 columns of the 100^3 matrix: 11.9 ms per step, against
+        // 13.2 ms with the multiply-add predicated and 13.7 ms with the tail gathers
+        // skipped)
         int c[U];
         typename Tr::val a[U];
-        bool ok[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            ok[u] = e0 + u < end;
-            const int e = ok[u] ? e0 + u : end - 1;
+            const bool ok = e0 + u < end;
+            const int e = ok ? e0 + u : end - 1;
             c[u] = ci[e];
-            a[u] = va[e];
+            a[u] = ok ? va[e] : Tr::val_zero();
         }
         vec w[U][VN];
 #pragma unroll
@@ -76,9 +80,8 @@ __global__ __launch_bounds__(256, 4) void clenshaw_batched_kernel(
             for (int v = 0; v < VN; ++v) w[u][v] = sp[v][(int64_t)c[u] * ldv + vix[v]];
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (ok[u])
 #pragma unroll
-                for (int v = 0; v < VN; ++v) acc[v] = Tr::fma_val(a[u], w[u][v], acc[v]);
+            for (int v = 0; v < VN; ++v) acc[v] = Tr::fma_val(a[u], w[u][v], acc[v]);
     }
 #pragma unroll
     for (int v = 0; v < VN; ++v) {

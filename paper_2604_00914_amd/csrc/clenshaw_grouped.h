@@ -41,7 +41,7 @@ __global__ __launch_bounds__(256) void clenshaw_grouped_kernel(
     const bool hv = args.has_v[g] != 0;
     const scal alpha = (scal)args.alpha[g];
     const bool hx = args.alpha[g] != 0.0;
-    constexpr bool EARLY = VN <= 3;
+    constexpr bool EARLY = L < 64 && VN <= 3;  // as in clenshaw_step_kernel
     const int64_t base = (int64_t)row * ldv + sub;
     vec vin[VN], xin[VN];
     if (EARLY) {
@@ -55,7 +55,7 @@ __global__ __launch_bounds__(256) void clenshaw_grouped_kernel(
     vec acc[VN];
 #pragma unroll
     for (int v = 0; v < VN; ++v) acc[v] = Tr::zero();
-    gather_accumulate<Tr, VN, U>(start, end, ci, va, src, ldv, sub, L, VN, acc);
+    gather_accumulate<Tr, VN, U, L == 64>(start, end, ci, va, src, ldv, sub, L, VN, acc);
 #pragma unroll
     for (int v = 0; v < VN; ++v) {
         const int64_t idx = base + v * L;

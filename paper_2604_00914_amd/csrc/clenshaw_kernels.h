@@ -11,8 +11,9 @@
 // each load instruction of the group reads L*16 contiguous bytes of a row.  The
 // row's (column, value) pairs are the same for every lane of the group (scalar
 // registers when L = 64).  U nonzeros are fetched together so that U*VN row
-// gathers are in flight per lane; the tail of a row is handled by clamping the
-// index and predicating the multiply-add, never by reading past the row.
+// gathers are in flight per lane; in the tail of a row the index is clamped (never
+// reading past the row) and the entry contributes nothing (gather_accumulate says
+// how, per lane mapping).
 // MASKED variants use L = 64 and loop over chunks of 64*VN vectors with a bounds
 // test, for any width.
 //
@@ -25,11 +26,11 @@
 //    of `group` workgroups (a few thousand rows) while all XCDs advance through
 //    the matrix together: neighbouring rows share an L2, and the far neighbours of
 //    a banded matrix are still in the shared memory-side cache when reused.
-//  * With at most 3 vectors per lane the in-place b_{j+2} and X are loaded before
-//    the row's CSR entries, so that they are in flight during the gathers; with
-//    more, the extra registers cost occupancy and the loads stay after the gathers
-//    (measured on the 100^3 stencil: 1.3% faster at 2 vectors per lane, 1.6%
-//    slower at 4).
+//  * With one row per wave the in-place b_{j+2} and X are loaded after the
+//    gathers: issuing them before the row's CSR entries (kept there by a compiler
+//    barrier) needs 96 VGPRs at 2 vectors per lane, 5 waves per SIMD instead of 8,
+//    and measured 2.5% slower on the 100^3 stencil.  With several rows per wave and
+//    at most 3 vectors per lane they are issued before the CSR entries.
 #pragma once
 
 #include "vec_types.h"
@@ -45,7 +46,15 @@ __device__ inline int xcd_block(int b, int group, int nblocks) {
     return lb < nblocks ? lb : -1;
 }
 
-template <class Tr, int VN, int U>
+// WAVE_ROW: every lane of the wave works on the same row (L = 64), so the tail
+// test is wave-uniform.  Then a tail gather is skipped by a uniform branch and its
+// vector left at zero, while the multiply-adds stay unconditional; predicating the
+// multiply-add instead lets the compiler move each gather into that branch, next to
+// its wait, and only one nonzero's gathers are in flight at a time.  With several
+// rows per wave (L < 64) the tail test differs between lanes, the gathers are
+// issued together under the execution mask either way, and the predicated
+// multiply-add is the faster form.
+template <class Tr, int VN, int U, bool WAVE_ROW>
 __device__ inline void gather_accumulate(int start, int end, const int *__restrict__ ci,
                                          const typename Tr::val *__restrict__ va,
                                          const typename Tr::vec *__restrict__ src, int64_t ldv,
@@ -69,12 +78,18 @@ __device__ inline void gather_accumulate(int start, int end, const int *__restri
         for (int u = 0; u < U; ++u) {
             const vec *rowp = src + (int64_t)c[u] * ldv + off;
 #pragma unroll
-            for (int v = 0; v < VN; ++v)
-                if (v < nvalid) w[u][v] = rowp[v * stride];
+            for (int v = 0; v < VN; ++v) {
+                if (WAVE_ROW) {
+                    w[u][v] = Tr::zero();
+                    if (ok[u] && v < nvalid) w[u][v] = rowp[v * stride];
+                } else if (v < nvalid) {
+                    w[u][v] = rowp[v * stride];
+                }
+            }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            if (ok[u]) {
+            if (WAVE_ROW || ok[u]) {
 #pragma unroll
                 for (int v = 0; v < VN; ++v)
                     if (v < nvalid) acc[v] = Tr::fma_val(a[u], w[u][v], acc[v]);
@@ -99,7 +114,7 @@ __global__ __launch_bounds__(256) void clenshaw_step_kernel(
     int row = (lb * (int)(blockDim.x / 64) + (int)(threadIdx.x >> 6)) * RW + lane / L;
     if (L == 64) row = __builtin_amdgcn_readfirstlane(row);
     if (row >= n) return;
-    constexpr bool EARLY = VN <= 3;
+    constexpr bool EARLY = L < 64 && VN <= 3;
     const int64_t base = (int64_t)row * ldv + sub;
     vec vin[VN], xin[VN];
     if (EARLY) {
@@ -113,7 +128,7 @@ __global__ __launch_bounds__(256) void clenshaw_step_kernel(
     vec acc[VN];
 #pragma unroll
     for (int v = 0; v < VN; ++v) acc[v] = Tr::zero();
-    gather_accumulate<Tr, VN, U>(start, end, ci, va, src, ldv, sub, L, VN, acc);
+    gather_accumulate<Tr, VN, U, L == 64>(start, end, ci, va, src, ldv, sub, L, VN, acc);
 #pragma unroll
     for (int v = 0; v < VN; ++v) {
         const int64_t idx = base + v * L;
@@ -147,7 +162,7 @@ __global__ __launch_bounds__(256) void clenshaw_step_masked_kernel(
         vec acc[VN];
 #pragma unroll
         for (int v = 0; v < VN; ++v) acc[v] = Tr::zero();
-        gather_accumulate<Tr, VN, U>(start, end, ci, va, src, ldv, c0 + lane, 64, nvalid, acc);
+        gather_accumulate<Tr, VN, U, true>(start, end, ci, va, src, ldv, c0 + lane, 64, nvalid, acc);
         const int64_t base = (int64_t)row * ldv + c0 + lane;
 #pragma unroll
         for (int v = 0; v < VN; ++v) {
@@ -184,7 +199,7 @@ __global__ __launch_bounds__(256) void clenshaw_step_scalar_kernel(
         vec acc[VN];
 #pragma unroll
         for (int v = 0; v < VN; ++v) acc[v] = Tr::zero();
-        gather_accumulate<Tr, VN, U>(start, end, ci, va, src, ld, c0 + lane, 64, nvalid, acc);
+        gather_accumulate<Tr, VN, U, true>(start, end, ci, va, src, ld, c0 + lane, 64, nvalid, acc);
         const int64_t base = (int64_t)row * ld + c0 + lane;
 #pragma unroll
         for (int v = 0; v < VN; ++v) {

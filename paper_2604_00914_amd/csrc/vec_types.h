@@ -18,6 +18,7 @@ struct TrR64 {
     using scal = double;
     static constexpr int E = 2;  // elements per vector
     __device__ static inline vec zero() { return make_double2(0.0, 0.0); }
+    __device__ static inline val val_zero() { return 0.0; }
     __device__ static inline vec fma_val(val a, vec w, vec acc) {
         acc.x = __builtin_fma(a, w.x, acc.x);
         acc.y = __builtin_fma(a, w.y, acc.y);
@@ -36,6 +37,7 @@ struct TrR32 {
     using scal = float;
     static constexpr int E = 4;
     __device__ static inline vec zero() { return make_float4(0.f, 0.f, 0.f, 0.f); }
+    __device__ static inline val val_zero() { return 0.f; }
     __device__ static inline vec fma_val(val a, vec w, vec acc) {
         acc.x = __builtin_fmaf(a, w.x, acc.x);
         acc.y = __builtin_fmaf(a, w.y, acc.y);
@@ -62,6 +64,7 @@ struct TrC128 {
     using scal = double;
     static constexpr int E = 1;
     __device__ static inline vec zero() { return make_double2(0.0, 0.0); }
+    __device__ static inline val val_zero() { return make_double2(0.0, 0.0); }
     __device__ static inline vec fma_val(val a, vec w, vec acc) {
         acc.x = __builtin_fma(a.x, w.x, acc.x);
         acc.x = __builtin_fma(-a.y, w.y, acc.x);
@@ -81,6 +84,7 @@ struct TrC64 {
     using scal = float;
     static constexpr int E = 2;
     __device__ static inline vec zero() { return make_float4(0.f, 0.f, 0.f, 0.f); }
+    __device__ static inline val val_zero() { return make_float2(0.f, 0.f); }
     __device__ static inline vec fma_val(val a, vec w, vec acc) {
         acc.x = __builtin_fmaf(a.x, w.x, acc.x);
         acc.x = __builtin_fmaf(-a.y, w.y, acc.x);
@@ -104,6 +108,7 @@ struct SR64 {
     using val = double;
     using scal = double;
     __device__ static inline vec zero() { return 0.0; }
+    __device__ static inline val val_zero() { return 0.0; }
     __device__ static inline vec fma_val(val a, vec w, vec acc) { return __builtin_fma(a, w, acc); }
     __device__ static inline vec scale(scal s, vec a) { return s * a; }
     __device__ static inline vec axpy(scal s, vec x, vec y) { return __builtin_fma(s, x, y); }
@@ -114,6 +119,7 @@ struct SR32 {
     using val = float;
     using scal = float;
     __device__ static inline vec zero() { return 0.f; }
+    __device__ static inline val val_zero() { return 0.f; }
     __device__ static inline vec fma_val(val a, vec w, vec acc) { return __builtin_fmaf(a, w, acc); }
     __device__ static inline vec scale(scal s, vec a) { return s * a; }
     __device__ static inline vec axpy(scal s, vec x, vec y) { return __builtin_fmaf(s, x, y); }
@@ -125,6 +131,7 @@ struct SC64 {
     using val = float2;
     using scal = float;
     __device__ static inline vec zero() { return make_float2(0.f, 0.f); }
+    __device__ static inline val val_zero() { return make_float2(0.f, 0.f); }
     __device__ static inline vec fma_val(val a, vec w, vec acc) {
         acc.x = __builtin_fmaf(a.x, w.x, acc.x);
         acc.x = __builtin_fmaf(-a.y, w.y, acc.x);
