@@ -14,6 +14,7 @@ from paper_2604_00914_amd import afsi
 from tests.gpu_util import DEV, max_rel, rel_fro, to_dev, torch
 from workloads import (
     build_config,
+    gershgorin_bounds,
     laplacian_3d_dirichlet,
     random_dense_symmetric_csr,
     start_block,
@@ -163,6 +164,64 @@ def test_ragged_and_degenerate_matrices():
         _check(got, oracle_filter(A, X0, -4.0, 4.0, -1.0, 1.5, 5), F64_TOL)
 
 
+def _ragged_symmetric(n=1001, seed=5, complex_=False):
+    """Symmetric (Hermitian) matrix whose row lengths run from 0 to ~34: every residue
+    mod 8 (the Clenshaw kernels fetch eight nonzeros at a time), exact multiples of 8,
+    rows longer than one and two fetch chunks, and empty rows and columns."""
+    from workloads import CSR
+
+    rng = np.random.default_rng(seed)
+    mask = np.triu(rng.uniform(size=(n, n)) < 0.0035, 1)
+    long_rows = np.zeros(n, bool)
+    long_rows[3::53] = True
+    mask |= np.triu(long_rows[:, None] & (rng.uniform(size=(n, n)) < 0.02), 1)
+    M = rng.standard_normal((n, n))
+    if complex_:
+        M = M + 1j * rng.standard_normal((n, n))
+    H = np.where(mask, M, 0)
+    H = H + H.conj().T + np.diag(rng.standard_normal(n))
+    H[::37, :] = 0
+    H[:, ::37] = 0
+    rows, cols = np.nonzero(H)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows, minlength=n), out=row_ptr[1:])
+    return CSR(n, row_ptr, cols.astype(np.int32), H[rows, cols])
+
+
+@pytest.mark.parametrize(
+    "p,single,cplx,pad,offset",
+    [
+        (256, False, False, 0, 0),   # 2 vectors x 64 lanes: one row per wave
+        (512, False, False, 0, 0),   # 4 x 64
+        (96, False, False, 0, 0),    # 3 x 16: four rows per wave
+        (64, False, False, 0, 0),    # 1 x 32
+        (128, False, False, 0, 0),   # 2 x 32
+        (192, False, False, 0, 0),   # 3 x 32
+        (100, False, False, 0, 0),   # no exact lane mapping: masked kernel
+        (64, False, False, 1, 1),    # 8-byte offset view: scalar kernel
+        (256, True, False, 0, 0),    # FP32, 2 x 32
+        (512, True, False, 0, 0),    # FP32, 2 x 64
+        (192, False, True, 0, 0),    # complex FP64, 3 x 64
+        (192, True, True, 0, 0),     # complex FP32, 3 x 32
+    ],
+)
+def test_ragged_row_lengths_every_lane_mapping(p, single, cplx, pad, offset):
+    A = _ragged_symmetric(complex_=cplx)
+    lengths = np.diff(A.row_ptr)
+    assert lengths.min() == 0 and lengths.max() >= 32
+    assert set(np.unique(lengths % 8)) == set(range(8))
+    lmin, lmax = gershgorin_bounds(A)
+    k = 12
+    c = afsi.afsi_filter_coefficients(lmin, lmax, -0.5, 0.7, k, "jackson")
+    X0 = start_block(A.n, p, seed=p + pad, complex_=cplx)
+    got = gpu_filter(A, X0, lmin, lmax, c, k, single=single, pad=pad, offset=offset)
+    ref = oracle_filter(A, X0, lmin, lmax, -0.5, 0.7, k)
+    if single:
+        assert rel_fro(got, ref) <= f32_tol(k), rel_fro(got, ref)
+    else:
+        _check(got, ref, F64_TOL)
+
+
 def test_repeatable_bitwise():
     A, (lmin, lmax), (a, b), cfg = build_config("lap2d_64")
     X0 = start_block(A.n, cfg.p, seed=3)
@@ -184,11 +243,16 @@ BATCH_LAYOUTS = {
 }
 
 
+@pytest.mark.parametrize("matrix", ["laplacian", "ragged"])
 @pytest.mark.parametrize("layout", sorted(BATCH_LAYOUTS))
-def test_batched_groups_bitwise_equal_to_single_filters(layout):
+def test_batched_groups_bitwise_equal_to_single_filters(layout, matrix):
     t = torch()
-    A = laplacian_3d_dirichlet(10, 2.0, seed=4)
-    lmin, lmax = 0.0, 14.0
+    if matrix == "ragged":
+        A = _ragged_symmetric()
+        lmin, lmax = gershgorin_bounds(A)
+    else:
+        A = laplacian_3d_dirichlet(10, 2.0, seed=4)
+        lmin, lmax = 0.0, 14.0
     l1, l2 = co.affine_map(lmin, lmax)
     ptot, groups = BATCH_LAYOUTS[layout]
     X0 = start_block(A.n, ptot, seed=5)
@@ -335,16 +399,17 @@ GROUPED = [(32, 32, 7, (3.0, 3.5), 0), (96, 104, 12, (5.0, 5.3), 1), (32, 32, 5,
            (3, 4, 4, (6.0, 6.2), 1)]
 
 
+@pytest.mark.parametrize("matrix", ["stencil", "ragged"])
 @pytest.mark.parametrize("cplx,single", [(False, False), (False, True), (True, False), (True, True)])
-def test_grouped_slices_bitwise_equal_to_single_filters(cplx, single):
+def test_grouped_slices_bitwise_equal_to_single_filters(cplx, single, matrix):
     t = torch()
     if cplx:
-        A = tight_binding_3d_periodic(8, seed=3)
-        lmin, lmax = -7.5, 7.5
+        A = tight_binding_3d_periodic(8, seed=3) if matrix == "stencil" else _ragged_symmetric(complex_=True)
+        lmin, lmax = (-7.5, 7.5) if matrix == "stencil" else gershgorin_bounds(A)
         groups = [(nc, ld, k, (iv[0] - 5.0, iv[1] - 5.0), st) for nc, ld, k, iv, st in GROUPED]
     else:
-        A = laplacian_3d_dirichlet(10, 2.0, seed=4)
-        lmin, lmax = 0.0, 14.0
+        A = laplacian_3d_dirichlet(10, 2.0, seed=4) if matrix == "stencil" else _ragged_symmetric()
+        lmin, lmax = (0.0, 14.0) if matrix == "stencil" else gershgorin_bounds(A)
         groups = GROUPED
     l1, l2 = co.affine_map(lmin, lmax)
     dt = _tdt(cplx, single)
