@@ -95,6 +95,7 @@ MatView matrix_view(afsi_matrix_t A, int block_dtype, hipStream_t stream) {
                  "block dtype %d does not match the matrix (%s)", block_dtype,
                  A->dtype == AFSI_C128 ? "complex" : "real");
     MatView v{A->n, A->d_rp, A->d_ci, A->d_val64};
+    v.stage_near = 2 * A->near_nnz >= A->n;
     if (!is_fp64(block_dtype)) {
         std::lock_guard<std::mutex> lk(A->mu);
         if (!A->d_val32) {
@@ -399,6 +400,7 @@ int afsi_matrix_create_csr(int device, int64_t n, int64_t nnz, const int64_t *ro
         AFSI_REQUIRE(nnz == 0 || (col_idx && vals), "col_idx / vals are NULL");
         AFSI_REQUIRE(row_ptr[0] == 0 && row_ptr[n] == nnz, "row_ptr must start at 0 and end at nnz");
         std::vector<int> rp32(n + 1);
+        int64_t near_nnz = 0;
         for (int64_t i = 0; i < n; ++i) {
             AFSI_REQUIRE(row_ptr[i + 1] >= row_ptr[i], "row_ptr decreases at row %lld", (long long)i);
             for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
@@ -406,6 +408,7 @@ int afsi_matrix_create_csr(int device, int64_t n, int64_t nnz, const int64_t *ro
                              col_idx[e], (long long)i);
                 AFSI_REQUIRE(e == row_ptr[i] || col_idx[e] > col_idx[e - 1],
                              "columns not strictly increasing in row %lld", (long long)i);
+                near_nnz += col_idx[e] >= i - 1 && col_idx[e] <= i + 1;
             }
             rp32[i] = (int)row_ptr[i];
         }
@@ -415,6 +418,7 @@ int afsi_matrix_create_csr(int device, int64_t n, int64_t nnz, const int64_t *ro
         A->device = device;
         A->n = n;
         A->nnz = nnz;
+        A->near_nnz = near_nnz;
         A->dtype = val_dtype;
         const size_t vbytes = (size_t)nnz * elem_bytes(val_dtype);
         try {

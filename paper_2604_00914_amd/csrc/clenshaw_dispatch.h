@@ -33,6 +33,16 @@ void launch_exact(const MatView &A, const void *src, const void *X, void *dst, i
     using scal = typename Tr::scal;
     constexpr int U = VN <= 4 ? 8 : 4;
     const Grid g = xcd_grid(A.n, 4 * (64 / L));
+    if constexpr (L == 64 && VN <= 3) {
+        if (A.stage_near) {
+            hipLaunchKernelGGL((clenshaw_step_staged_kernel<Tr, VN, HV, HX, U>),
+                               dim3((unsigned)g.grid), dim3(256), 0, s, (int)A.n, A.rp, A.ci,
+                               (const typename Tr::val *)A.val, (const vec *)src, (const vec *)X,
+                               (vec *)dst, ldv, (scal)sigma, (scal)tau, (scal)alpha, g.group,
+                               g.nblocks);
+            return;
+        }
+    }
     hipLaunchKernelGGL((clenshaw_step_kernel<Tr, VN, L, HV, HX, U>), dim3((unsigned)g.grid),
                        dim3(256), 0, s, (int)A.n, A.rp, A.ci, (const typename Tr::val *)A.val,
                        (const vec *)src, (const vec *)X, (vec *)dst, ldv, (scal)sigma, (scal)tau,

@@ -83,6 +83,9 @@ struct MatView {
     const int *rp;   // n + 1
     const int *ci;   // nnz
     const void *val; // nnz values of the requested precision
+    // at least one entry per two rows lies within one column of the diagonal: the
+    // Clenshaw step stages each workgroup's rows of the source block in LDS
+    bool stage_near = false;
 };
 
 }  // namespace afsi
@@ -95,6 +98,7 @@ struct afsi_matrix_s {
     int *d_ci = nullptr;
     void *d_val64 = nullptr;
     void *d_val32 = nullptr;
+    int64_t near_nnz = 0;  // entries with |column - row| <= 1
     double lmin = 0, lmax = 0;
     bool has_bounds = false;
     std::mutex mu;
