@@ -307,7 +307,7 @@ def main():
         "dominant_frac_of_copy": round(achieved / copy_gbs, 4),
         "dominant_frac_of_3r1w": round(achieved / stream3_gbs, 4),
         "roofline": {
-            "kernel": "clenshaw_step_kernel<HAS_V=1,HAS_X=1> (gather src, read V in place, read X, write V)",
+            "kernel": "clenshaw_step_staged_kernel<HAS_V=1,HAS_X=1> (gather src, read V in place, read X, write V)",
             "launches": steady_launches,
             "bound": "hbm",
             "achieved": round(achieved, 1),

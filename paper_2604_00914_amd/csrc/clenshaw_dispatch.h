@@ -33,9 +33,9 @@ void launch_exact(const MatView &A, const void *src, const void *X, void *dst, i
     using scal = typename Tr::scal;
     constexpr int U = VN <= 4 ? 8 : 4;
     const Grid g = xcd_grid(A.n, 4 * (64 / L));
-    if constexpr (L == 64 && VN <= 3) {
+    if constexpr (VN <= 3 && L == 64) {
         if (A.stage_near) {
-            hipLaunchKernelGGL((clenshaw_step_staged_kernel<Tr, VN, HV, HX, U>),
+            hipLaunchKernelGGL((clenshaw_step_staged_kernel<Tr, VN, L, HV, HX, U>),
                                dim3((unsigned)g.grid), dim3(256), 0, s, (int)A.n, A.rp, A.ci,
                                (const typename Tr::val *)A.val, (const vec *)src, (const vec *)X,
                                (vec *)dst, ldv, (scal)sigma, (scal)tau, (scal)alpha, g.group,
@@ -69,6 +69,10 @@ void dispatch_flags(const MatView &A, const void *src, const void *X, void *dst,
     // 100^3 stencil: 2 x 64 over 4 x 32 at 128 vectors, 2 x 32 over 1 x 64 at 64)
 #define AFSI_EXACT(VN_, L_)                                                                         \
     if (p16 == (VN_) * (L_)) return launch_exact<Tr, VN_, L_, HV, HX>(A, src, X, dst, ldv, sg, ta, al, s)
+    // with near-diagonal entries one row per wave takes the LDS-staged kernel, which at
+    // 64 vectors per row (FP32 p = 256) beats two rows per wave: 810 against 847 us on
+    // the 100^3 stencil
+    if (A.stage_near) { AFSI_EXACT(1, 64); }
     AFSI_EXACT(2, 64); AFSI_EXACT(4, 32); AFSI_EXACT(4, 64); AFSI_EXACT(3, 64); AFSI_EXACT(5, 64);
     AFSI_EXACT(3, 32); AFSI_EXACT(5, 32); AFSI_EXACT(2, 32);
     AFSI_EXACT(6, 64); AFSI_EXACT(8, 64); AFSI_EXACT(1, 64); AFSI_EXACT(1, 32);

@@ -15,7 +15,7 @@
 
 namespace afsi {
 
-template <class Tr, int VN, int L, int U>
+template <class Tr, int VN, int L, int U, bool STAGE>
 __global__ __launch_bounds__(256) void clenshaw_grouped_kernel(
     int n, const int *__restrict__ rp, const int *__restrict__ ci,
     const typename Tr::val *__restrict__ va, int group, int nblocks, const GroupArgs args) {
@@ -27,6 +27,18 @@ __global__ __launch_bounds__(256) void clenshaw_grouped_kernel(
     const int64_t r0 = (int64_t)lb * (4 * RW);
     const int g = __builtin_amdgcn_readfirstlane((int)(r0 / args.npad));
     if (g >= args.ngroups) return;
+    if constexpr (STAGE) {  // the slice's rows of its source block in LDS (staged_step)
+        __shared__ vec tile[Staged<Tr, VN, L>::NSV];
+        const int s = args.src[g];
+        const vec *X = (const vec *)args.X[g];
+        vec *P0 = (vec *)args.P0[g], *P1 = (vec *)args.P1[g];
+        staged_step<Tr, VN, L, U>(n, (int)(r0 - (int64_t)g * args.npad), rp, ci, va,
+                                  s == 0 ? X : (s == 1 ? P0 : P1), X, args.dst[g] == 1 ? P0 : P1,
+                                  args.ldv[g], (scal)args.sigma[g], (scal)args.tau[g],
+                                  (scal)args.alpha[g], args.has_v[g] != 0, args.alpha[g] != 0.0,
+                                  tile);
+        return;
+    }
     const int lane = threadIdx.x & 63;
     const int sub = lane % L;
     int row = (int)(r0 - (int64_t)g * args.npad) + (int)(threadIdx.x >> 6) * RW + lane / L;
@@ -74,9 +86,17 @@ void launch_grouped(const MatView &A, GroupArgs &args, hipStream_t s) {
     const int64_t rows = args.npad * args.ngroups;
     AFSI_REQUIRE(rows / rows_per_block < (1LL << 31), "grouped step: too many rows");
     const Grid g = xcd_grid(rows, rows_per_block);
-    hipLaunchKernelGGL((clenshaw_grouped_kernel<Tr, VN, L, U>), dim3((unsigned)g.grid), dim3(256),
-                       0, s, (int)A.n, A.rp, A.ci, (const typename Tr::val *)A.val, g.group,
-                       g.nblocks, args);
+    if constexpr (VN <= 3 && L == 64) {
+        if (A.stage_near) {
+            hipLaunchKernelGGL((clenshaw_grouped_kernel<Tr, VN, L, U, true>), dim3((unsigned)g.grid),
+                               dim3(256), 0, s, (int)A.n, A.rp, A.ci,
+                               (const typename Tr::val *)A.val, g.group, g.nblocks, args);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((clenshaw_grouped_kernel<Tr, VN, L, U, false>), dim3((unsigned)g.grid),
+                       dim3(256), 0, s, (int)A.n, A.rp, A.ci, (const typename Tr::val *)A.val,
+                       g.group, g.nblocks, args);
 }
 
 // true if p16 has an exact lane mapping (the single-block kernel's table, same order)
@@ -84,6 +104,7 @@ template <class Tr>
 bool dispatch_grouped(const MatView &A, int p16, GroupArgs &args, hipStream_t s) {
 #define AFSI_GROUPED(VN_, L_)                                                                       \
     if (p16 == (VN_) * (L_)) return launch_grouped<Tr, VN_, L_>(A, args, s), true
+    if (A.stage_near) { AFSI_GROUPED(1, 64); }  // as in dispatch_flags
     AFSI_GROUPED(2, 64); AFSI_GROUPED(4, 32); AFSI_GROUPED(4, 64); AFSI_GROUPED(3, 64);
     AFSI_GROUPED(5, 64); AFSI_GROUPED(3, 32); AFSI_GROUPED(5, 32); AFSI_GROUPED(2, 32);
     AFSI_GROUPED(6, 64); AFSI_GROUPED(8, 64); AFSI_GROUPED(1, 64); AFSI_GROUPED(1, 32);

@@ -139,46 +139,57 @@ __global__ __launch_bounds__(256) void clenshaw_step_kernel(
     }
 }
 
-// One row per wave (L = 64) with the source rows of the workgroup staged in LDS.
-// The workgroup's four rows are consecutive (the same row mapping as
-// clenshaw_step_kernel at L = 64), so src rows r0 - 1 .. r0 + 4 are copied to LDS
-// once and every entry whose column falls among them, and the tau * src_i term, read
-// LDS instead of gathering through L1/L2.  The stencil's diagonal and +-1 entries (3
-// of 7 per row) take this path: 1660 -> 1597 us per product on the 100^3 stencil at
-// p = 256 FP64 in a standalone measurement; four rows per workgroup measured faster
-// than 2, 8 or 16.  The staging loads are issued first and the gathers from global
-// memory of the row's first U entries before the barrier, so both are in flight
+// Rows of the source block staged in LDS.  A workgroup's 4 * (64 / L) rows are
+// consecutive (the row mapping of clenshaw_step_kernel), so src rows r0 - 1 .. r0 + TR
+// are copied to LDS once and every entry whose column falls among them, and the
+// tau * src_i term, read LDS instead of gathering through L1/L2.  The stencil's
+// diagonal and +-1 entries (3 of 7 per row) take this path: 1664 -> 1598 us per
+// product on the 100^3 stencil at p = 256 FP64, 684 -> 628 us on the 64^3 complex
+// lattice at p = 192; four rows per workgroup measured faster than 2, 8 or 16 at one
+// row per wave.  The staging loads are issued first and the gathers from global
+// memory of a row's first U entries before the barrier, so both are in flight
 // together; entries past the first U follow in gather_accumulate (no LDS).  The
 // multiply-adds run in entry order, as in gather_accumulate, so a column's bits do
-// not depend on the kernel.  Staging passes through registers: used for VN <= 3.
-template <class Tr, int VN, bool HAS_V, bool HAS_X, int U>
-__global__ __launch_bounds__(256) void clenshaw_step_staged_kernel(
-    int n, const int *__restrict__ rp, const int *__restrict__ ci,
-    const typename Tr::val *__restrict__ va, const typename Tr::vec *__restrict__ src,
-    const typename Tr::vec *__restrict__ X, typename Tr::vec *dst, int64_t ldv,
-    typename Tr::scal sigma, typename Tr::scal tau, typename Tr::scal alpha, int group,
-    int nblocks) {
+// not depend on the kernel.  Staging passes through registers: used for VN <= 3, and
+// at one row per wave only (the routine handles narrower lane groups, but staged they
+// measured slower: 3 x 32 complex FP32 361 -> 384 us, the 3 x 16 grouped slice step
+// 11.2 -> 14.5 ms).
+template <class Tr, int VN, int L>
+struct Staged {
+    static constexpr int RW = 64 / L;        // rows per wave
+    static constexpr int TR = 4 * RW;        // rows per workgroup
+    static constexpr int RV = VN * L;        // vectors per row
+    static constexpr int NSV = (TR + 2) * RV;  // staged vectors
+    static constexpr int NS = (NSV + 255) / 256;
+};
+
+// One workgroup of staged_step: rows rb .. rb + TR - 1 of an n-row block (rb >= 0).
+// Every thread of the workgroup must call it (it holds a barrier).
+template <class Tr, int VN, int L, int U>
+__device__ __forceinline__ void staged_step(int n, int rb, const int *__restrict__ rp,
+                                   const int *__restrict__ ci,
+                                   const typename Tr::val *__restrict__ va,
+                                   const typename Tr::vec *__restrict__ src,
+                                   const typename Tr::vec *__restrict__ X, typename Tr::vec *dst,
+                                   int64_t ldv, typename Tr::scal sigma, typename Tr::scal tau,
+                                   typename Tr::scal alpha, bool hv, bool hx,
+                                   typename Tr::vec *tile) {
     using vec = typename Tr::vec;
     using val = typename Tr::val;
-    constexpr int RV = 64 * VN;            // vectors per row
-    constexpr int TR = 4;                  // rows per workgroup
-    constexpr int NSV = (TR + 2) * RV;     // staged vectors
-    constexpr int NS = (NSV + 255) / 256;  // staged vectors per thread
-    __shared__ vec tile[NSV];
-    const int lb = xcd_block(blockIdx.x, group, nblocks);
-    if (lb < 0) return;  // the whole workgroup: before the barrier
+    using S = Staged<Tr, VN, L>;
     const int lane = threadIdx.x & 63;
-    const int wlo = lb * TR - 1;  // first staged row
-    vec stage[NS];
+    const int sub = lane % L;
+    const int wlo = rb - 1;  // first staged row
+    vec stage[S::NS];
 #pragma unroll
-    for (int j = 0; j < NS; ++j) {
+    for (int j = 0; j < S::NS; ++j) {
         const int k = (int)threadIdx.x + 256 * j;
-        const int rr = wlo + k / RV;
+        const int rr = wlo + k / S::RV;
         stage[j] = Tr::zero();
-        if (k < NSV && rr >= 0 && rr < n) stage[j] = src[(int64_t)rr * ldv + k % RV];
+        if (k < S::NSV && rr >= 0 && rr < n) stage[j] = src[(int64_t)rr * ldv + k % S::RV];
     }
-    int row = lb * TR + (int)(threadIdx.x >> 6);
-    row = __builtin_amdgcn_readfirstlane(row);
+    int row = rb + (int)(threadIdx.x >> 6) * S::RW + lane / L;
+    if (L == 64) row = __builtin_amdgcn_readfirstlane(row);
     const bool live = row < n;
     const int start = live ? rp[row] : 0, end = live ? rp[row + 1] : 0;
     vec acc[VN];
@@ -193,39 +204,53 @@ __global__ __launch_bounds__(256) void clenshaw_step_staged_kernel(
         const bool ok = start + u < end;
         c[u] = ok ? ci[start + u] : 0;
         a[u] = ok ? va[start + u] : Tr::val_zero();
-        near[u] = ok && c[u] >= wlo && c[u] <= wlo + TR + 1;
+        near[u] = ok && c[u] >= wlo && c[u] <= wlo + S::TR + 1;
 #pragma unroll
         for (int v = 0; v < VN; ++v) {
             w[u][v] = Tr::zero();
-            if (ok && !near[u]) w[u][v] = src[(int64_t)c[u] * ldv + lane + v * 64];
+            if (ok && !near[u]) w[u][v] = src[(int64_t)c[u] * ldv + sub + v * L];
         }
     }
 #pragma unroll
-    for (int j = 0; j < NS; ++j) {
+    for (int j = 0; j < S::NS; ++j) {
         const int k = (int)threadIdx.x + 256 * j;
-        if (k < NSV) tile[k] = stage[j];
+        if (k < S::NSV) tile[k] = stage[j];
     }
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
         for (int v = 0; v < VN; ++v)
-            if (near[u]) w[u][v] = tile[(c[u] - wlo) * RV + lane + v * 64];
+            if (near[u]) w[u][v] = tile[(c[u] - wlo) * S::RV + sub + v * L];
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
         for (int v = 0; v < VN; ++v) acc[v] = Tr::fma_val(a[u], w[u][v], acc[v]);
-    gather_accumulate<Tr, VN, U, true>(start + U, end, ci, va, src, ldv, lane, 64, VN, acc);
+    gather_accumulate<Tr, VN, U, L == 64>(start + U, end, ci, va, src, ldv, sub, L, VN, acc);
     if (!live) return;
-    const int64_t base = (int64_t)row * ldv + lane;
+    const int64_t base = (int64_t)row * ldv + sub;
 #pragma unroll
     for (int v = 0; v < VN; ++v) {
-        const int64_t idx = base + v * 64;
-        vec r = clenshaw_combine<Tr>(sigma, tau, acc[v], tile[(row - wlo) * RV + lane + v * 64]);
-        if (HAS_V) r = Tr::sub(r, nt_load(dst + idx));
-        if (HAS_X) r = Tr::axpy(alpha, nt_load(X + idx), r);
+        const int64_t idx = base + v * L;
+        vec r = clenshaw_combine<Tr>(sigma, tau, acc[v], tile[(row - wlo) * S::RV + sub + v * L]);
+        if (hv) r = Tr::sub(r, nt_load(dst + idx));
+        if (hx) r = Tr::axpy(alpha, nt_load(X + idx), r);
         nt_store(r, dst + idx);
     }
+}
+
+template <class Tr, int VN, int L, bool HAS_V, bool HAS_X, int U>
+__global__ __launch_bounds__(256) void clenshaw_step_staged_kernel(
+    int n, const int *__restrict__ rp, const int *__restrict__ ci,
+    const typename Tr::val *__restrict__ va, const typename Tr::vec *__restrict__ src,
+    const typename Tr::vec *__restrict__ X, typename Tr::vec *dst, int64_t ldv,
+    typename Tr::scal sigma, typename Tr::scal tau, typename Tr::scal alpha, int group,
+    int nblocks) {
+    __shared__ typename Tr::vec tile[Staged<Tr, VN, L>::NSV];
+    const int lb = xcd_block(blockIdx.x, group, nblocks);
+    if (lb < 0) return;  // the whole workgroup: before the barrier
+    staged_step<Tr, VN, L, U>(n, lb * Staged<Tr, VN, L>::TR, rp, ci, va, src, X, dst, ldv, sigma,
+                              tau, alpha, HAS_V, HAS_X, tile);
 }
 
 // Any width: L = 64 lanes per row, chunks of 64*VN vectors, bounds-tested.
