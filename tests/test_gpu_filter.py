@@ -222,6 +222,37 @@ def test_ragged_row_lengths_every_lane_mapping(p, single, cplx, pad, offset):
         _check(got, ref, F64_TOL)
 
 
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 6, 9])
+@pytest.mark.parametrize("p,single,cplx", [(256, False, False), (256, True, False), (192, False, True)])
+def test_staged_step_small_n(n, p, single, cplx):
+    # one row per wave with the source rows staged in LDS: workgroups whose rows run past
+    # n and staging windows clipped at row 0 and row n - 1 (tridiagonal plus a corner entry)
+    from workloads import CSR
+
+    rng = np.random.default_rng(n)
+    H = np.diag(rng.standard_normal(n) + 2.0).astype(np.complex128 if cplx else np.float64)
+    for i in range(n - 1):
+        z = rng.standard_normal() + (1j * rng.standard_normal() if cplx else 0.0)
+        H[i, i + 1], H[i + 1, i] = z, np.conj(z)
+    if n > 2:
+        H[0, n - 1] = H[n - 1, 0] = 0.5
+    rows, cols = np.nonzero(H)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows, minlength=n), out=row_ptr[1:])
+    A = CSR(n, row_ptr, cols.astype(np.int32), H[rows, cols])
+    lmin, lmax = gershgorin_bounds(A)
+    lmin, lmax = lmin - 1.0, lmax + 1.0  # n = 1: Gershgorin's interval is a point
+    X0 = start_block(n, p, seed=n, complex_=cplx)
+    k = 7
+    c = afsi.afsi_filter_coefficients(lmin, lmax, lmin + 0.3 * (lmax - lmin), lmin + 0.6 * (lmax - lmin), k, "jackson")
+    got = gpu_filter(A, X0, lmin, lmax, c, k, single=single)
+    ref = oracle_filter(A, X0, lmin, lmax, lmin + 0.3 * (lmax - lmin), lmin + 0.6 * (lmax - lmin), k)
+    if single:
+        assert rel_fro(got, ref) <= f32_tol(k), rel_fro(got, ref)
+    else:
+        _check(got, ref, F64_TOL)
+
+
 def test_repeatable_bitwise():
     A, (lmin, lmax), (a, b), cfg = build_config("lap2d_64")
     X0 = start_block(A.n, cfg.p, seed=3)
