@@ -80,7 +80,11 @@ int afsi_device_count(void);
 /* ------------------------------------------------------------------ matrices */
 
 /*
- * Copy a square Hermitian CSR matrix from host memory to device `device`.
+ * Copy a square Hermitian CSR matrix from host memory to device `device`.  CSR is the
+ * storage in which Section 3.3.1 keeps the sparse A of the filter's products (the
+ * row-pointer / column-index / value arrays its SpMM traverses row by row); the
+ * device copy is what every product of the filter, Rayleigh-Ritz and the residual
+ * step reads.
  *   row_ptr[n+1] (int64, row_ptr[0] = 0, non-decreasing, row_ptr[n] = nnz),
  *   col_idx[nnz] (int32, strictly increasing within each row, in [0, n)),
  *   vals[nnz]    (val_dtype AFSI_R64: double; AFSI_C128: interleaved re,im doubles).
@@ -168,6 +172,14 @@ int afsi_estimate_eigencount(afsi_matrix_t A, double a, double b, int degree, in
                              double m_exp, const afsi_block *Z, afsi_block *Y, afsi_block *work,
                              double *per_probe, double *estimate, void *stream);
 
+/*
+ * Block width from an eigenvalue-count estimate (Section 3.4: the subspace must hold
+ * at least the e eigenvalues of [a, b], so p = ceil(mu * e~) with mu > 0; Section 4
+ * uses mu = 1.8).  *p_out = ceil(mu * estimate), clipped to [1, n].  Needs mu > 0,
+ * n >= 1 and a finite estimate (a negative estimate gives 1).  Pure host function.
+ */
+int afsi_block_size(double estimate, double mu, int64_t n, int64_t *p_out);
+
 /* Y = A X (one sparse x dense-block product). X and Y as for afsi_filter_block. */
 int afsi_spmm(afsi_matrix_t A, const afsi_block *X, afsi_block *Y, void *stream);
 
@@ -193,8 +205,10 @@ int afsi_clenshaw_step_params(const double *coeffs, int degree, int step, double
                               afsi_step_group *g);
 
 /*
- * Batched step for spectrum slices of one matrix (several filters advanced
- * together, A read once).  X, P0, P1: n x ptot blocks of one dtype.  Groups must
+ * Batched step for spectrum slices of one matrix (Section 1: the interval of interest
+ * split into slices, each solved by its own filter; here several slices' Clenshaw
+ * recurrences of Algorithm 2 advance together and A is read once per product).
+ * X, P0, P1: n x ptot blocks of one dtype.  Groups must
  * not overlap; at most 64.  Columns outside every active group are untouched.
  * Per column the arithmetic is identical to afsi_filter_block's, so a slice gives
  * bit-identical results alone or batched.
@@ -203,7 +217,8 @@ int afsi_clenshaw_step_batched(afsi_matrix_t A, int ngroups, const afsi_step_gro
                                const afsi_block *X, afsi_block *P0, afsi_block *P1, void *stream);
 
 /*
- * Grouped step for spectrum slices of one matrix that keep their blocks apart: one
+ * Grouped step for spectrum slices of one matrix (Section 1's slicing; one product of
+ * Algorithm 2's recurrence per slice) that keep their blocks apart: one
  * product of every active slice, each on its own n x step.ncols blocks X, P0, P1
  * (row-major, leading dimension ld, device, `dtype` R64/R32 for a real A, C128/C64
  * for a complex A).  step holds the product's parameters exactly as for
@@ -222,6 +237,33 @@ typedef struct {
 
 int afsi_clenshaw_step_grouped(afsi_matrix_t A, int ngroups, const afsi_slice_blocks *slices,
                                int32_t dtype, void *stream);
+
+/*
+ * Whole filters of several spectrum slices of one matrix (Section 1's slicing, each
+ * slice filtered by Algorithm 2 with its own interval's coefficients): for every
+ * slice g, Y_g = sum_{j=0}^{degree_g} coeffs_g[j] T_j(l(A)) X_g.  The library runs
+ * the slices' recurrences side by side, one afsi_clenshaw_step_grouped product per
+ * step for all slices that still have products left (slices start together; a
+ * lower-degree slice finishes earlier), so A is read once per step for all of them.
+ * Every column gets the same bits as from afsi_filter_block on that slice alone.
+ *   coeffs : host, degree + 1 doubles (read before return).
+ *   X, Y, work : device, n x ncols, row-major with leading dimension ld (elements),
+ *   all of `dtype` (R64 / R32 for a real A, C128 / C64 for a complex A).  Y and work
+ *   are overwritten; X is read only.  No block may overlap another block of any slice.
+ * Needs spectral bounds on A and degree >= 1 for every slice.  Any number of slices.
+ * Errors: AFSI_E_INVALID.  Asynchronous on `stream`.
+ */
+typedef struct {
+    const double *coeffs;
+    int32_t degree;
+    const void *X;
+    void *Y;
+    void *work;
+    int64_t ncols, ld;
+} afsi_slice_filter;
+
+int afsi_filter_batched(afsi_matrix_t A, int nslices, const afsi_slice_filter *slices,
+                        int32_t dtype, void *stream);
 
 /* ------------------------------------------------------------------ dense steps (FP64) */
 
@@ -357,6 +399,64 @@ int afsi_solve(afsi_matrix_t A, double a, double b, const afsi_options *opts, af
                afsi_block *evecs, int64_t capacity, double *eigenvalues, double *residuals,
                afsi_result *result, void *stream);
 
+/* ------------------------------------------------------------------ filtered Lanczos */
+
+/*
+ * Filtered thick-restart block Lanczos.  Section 3.1 builds the damped filter for
+ * subspace iteration and notes that it suits thick-restart Lanczos as well (Section 5
+ * names filtered Lanczos as the framework to follow); the paper defines no such
+ * method, so this is the library's: a block Krylov method on the operator
+ * B = rho(A), the filter of eq. (AdaPolySI) at a fixed degree applied by Clenshaw's
+ * recurrence (Algorithm 2), whose eigenvalues rho(lambda) are close to one inside
+ * [a, b] and close to zero away from it.  Each cycle grows a basis of `basis` columns
+ * in blocks of `block` (every new block B V_last projected twice against the basis and
+ * the locked vectors, then Cholesky QR), does Rayleigh-Ritz on B (H = V^H B V, host
+ * eigensolver, theta descending), takes lambda = u^H A u and ||A u - lambda u|| for
+ * each Ritz vector u, and locks the pairs with theta >= eta = min(rho(a), rho(b)) and
+ * ||A u - lambda u|| < tau_c ||A|| (||A|| = max(|lmin|, |lmax|)); locked pairs with
+ * lambda in [a, b] are the results, the others are only deflated.  It stops when no
+ * pair with theta >= eta is left unlocked and the largest remaining theta plus its
+ * B-residual lies below eta; otherwise it restarts with the min(wanted + block,
+ * basis / 2) unlocked Ritz vectors of largest theta plus the next Krylov block.  A
+ * block of s columns finds eigenvalues of multiplicity up to s directly.
+ */
+typedef struct {
+    int32_t degree;      /* filter degree k (coefficients and damping at k) */
+    int32_t damping;     /* afsi_damping */
+    double m_exp;        /* exponent m for AFSI_DAMP_LANCZOS */
+    int32_t block;       /* s >= 1: columns per Krylov block */
+    int32_t basis;       /* m: basis columns before a restart, 2 s <= m <= n */
+    double tau_c;        /* lock when ||A u - lambda u|| < tau_c ||A|| */
+    int32_t max_cycles;  /* restart-cycle limit */
+} afsi_lanczos_options;
+
+/* Jackson damping, block 4, basis 128, tau_c 1e-10, 200 cycles, at degree `degree`. */
+void afsi_lanczos_options_default(afsi_lanczos_options *o, int degree);
+
+typedef struct {
+    int64_t count;           /* eigenpairs found in [a, b] */
+    int32_t cycles;
+    int32_t converged;       /* 1 if the stopping test held */
+    int64_t filter_columns;  /* columns the filter was applied to (each: `degree` products) */
+    int64_t locked_outside;  /* converged pairs outside [a, b] (deflated, not returned) */
+    double time_ms;
+} afsi_lanczos_result;
+
+/*
+ * Run the method above on A (bounds set) for [a, b].  X0: n x block start block
+ * (device, R64 for a real A, C128 for a complex A; read only).  On return:
+ * eigenvalues[count] and residuals[count] (host, ascending), eigenvectors in columns
+ * 0..count-1 of `evecs` (device, n x capacity, X0's dtype).  The library allocates its
+ * working blocks (five n x (basis + block) blocks and one n x basis block) for the
+ * call.  Returns AFSI_E_NOCONV with the pairs found if max_cycles is reached,
+ * AFSI_E_INVALID on bad arguments or if more than `capacity` pairs lock.
+ * Synchronises `stream`.
+ */
+int afsi_filtered_lanczos(afsi_matrix_t A, double a, double b, const afsi_lanczos_options *opts,
+                          const afsi_block *X0, afsi_block *evecs, int64_t capacity,
+                          double *eigenvalues, double *residuals, afsi_lanczos_result *result,
+                          void *stream);
+
 /* ------------------------------------------------------------------ serving */
 
 /*
@@ -367,9 +467,12 @@ int afsi_solve(afsi_matrix_t A, double a, double b, const afsi_options *opts, af
  * which a request owns a contiguous n x w slot of each, plus n x p for the
  * request's eigenvectors.  All filtering requests of a pool advance together, one
  * grouped Clenshaw product (afsi_clenshaw_step_grouped, one launch per width) per
- * round; each pool runs on its own HIP stream and host thread, so independent
- * matrices overlap on the device.  A request's results do not depend on what
- * else is running.  Matrices must outlive the requests that use them.
+ * round, on the pool's product stream and thread; the dense steps of Algorithm 4
+ * (orthonormalisation, Rayleigh-Ritz, residuals, locking) of a request whose filter
+ * has finished run on the pool's second stream and thread, while the other requests'
+ * products go on.  Independent matrices have their own pools and overlap on the
+ * device.  A request's results do not depend on what else is running.  Matrices must
+ * outlive the requests that use them.
  */
 typedef struct afsi_server_s *afsi_server_t;
 
@@ -388,6 +491,10 @@ typedef struct {
     int64_t bytes_in_use, budget;
     int64_t queued, running, done, pools;
     int64_t batched_launches, batched_groups; /* grouped rounds; slices per round = groups / launches */
+    int64_t kernel_launches, kernel_slices;   /* launches of the grouped kernel and the slice
+                                                 products they took (slices sharing one launch =
+                                                 kernel_slices / kernel_launches); the rest of a
+                                                 round's slices ran one product each */
     double now;                               /* server clock (s) */
 } afsi_server_stats;
 

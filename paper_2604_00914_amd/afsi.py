@@ -62,6 +62,17 @@ class afsi_result(C.Structure):
                 ("time_host_ms", C.c_double)]
 
 
+class afsi_lanczos_options(C.Structure):
+    _fields_ = [("degree", C.c_int32), ("damping", C.c_int32), ("m_exp", C.c_double),
+                ("block", C.c_int32), ("basis", C.c_int32), ("tau_c", C.c_double),
+                ("max_cycles", C.c_int32)]
+
+
+class afsi_lanczos_result(C.Structure):
+    _fields_ = [("count", C.c_int64), ("cycles", C.c_int32), ("converged", C.c_int32),
+                ("filter_columns", C.c_int64), ("locked_outside", C.c_int64), ("time_ms", C.c_double)]
+
+
 class afsi_request_info(C.Structure):
     _fields_ = [("state", C.c_int32), ("status", C.c_int32), ("count", C.c_int64),
                 ("iterations", C.c_int32), ("converged", C.c_int32), ("spmv", C.c_int64),
@@ -72,7 +83,13 @@ class afsi_request_info(C.Structure):
 class afsi_server_stats(C.Structure):
     _fields_ = [("bytes_in_use", C.c_int64), ("budget", C.c_int64), ("queued", C.c_int64),
                 ("running", C.c_int64), ("done", C.c_int64), ("pools", C.c_int64),
-                ("batched_launches", C.c_int64), ("batched_groups", C.c_int64), ("now", C.c_double)]
+                ("batched_launches", C.c_int64), ("batched_groups", C.c_int64),
+                ("kernel_launches", C.c_int64), ("kernel_slices", C.c_int64), ("now", C.c_double)]
+
+
+class afsi_slice_filter(C.Structure):
+    _fields_ = [("coeffs", C.c_void_p), ("degree", C.c_int32), ("X", C.c_void_p), ("Y", C.c_void_p),
+                ("work", C.c_void_p), ("ncols", C.c_int64), ("ld", C.c_int64)]
 
 
 _P = C.c_void_p
@@ -97,6 +114,8 @@ _SIGS = {
     "afsi_clenshaw_step_params": (C.c_int, [_P, C.c_int, C.c_int, C.c_double, C.c_double, C.POINTER(afsi_step_group)]),
     "afsi_clenshaw_step_batched": (C.c_int, [_P, C.c_int, C.POINTER(afsi_step_group), _BP, _BP, _BP, _P]),
     "afsi_clenshaw_step_grouped": (C.c_int, [_P, C.c_int, C.POINTER(afsi_slice_blocks), C.c_int32, _P]),
+    "afsi_filter_batched": (C.c_int, [_P, C.c_int, C.POINTER(afsi_slice_filter), C.c_int32, _P]),
+    "afsi_block_size": (C.c_int, [C.c_double, C.c_double, C.c_int64, _I64P]),
     "afsi_block_inner": (C.c_int, [_BP, _BP, _BP, _P]),
     "afsi_block_gemm": (C.c_int, [_BP, _BP, C.c_double, _BP, _P]),
     "afsi_orthonormalize": (C.c_int, [_BP, _BP, _BP, _P]),
@@ -110,6 +129,8 @@ _SIGS = {
     "afsi_host_cholesky_inverse": (C.c_int, [C.c_int64, C.c_int32, _P, C.c_int64, C.c_double]),
     "afsi_options_default": (None, [C.POINTER(afsi_options), C.c_int]),
     "afsi_solve": (C.c_int, [_P, C.c_double, C.c_double, C.POINTER(afsi_options), _BP, _BP, C.c_int64, _P, _P, C.POINTER(afsi_result), _P]),
+    "afsi_lanczos_options_default": (None, [C.POINTER(afsi_lanczos_options), C.c_int]),
+    "afsi_filtered_lanczos": (C.c_int, [_P, C.c_double, C.c_double, C.POINTER(afsi_lanczos_options), _BP, _BP, C.c_int64, _P, _P, C.POINTER(afsi_lanczos_result), _P]),
     "afsi_server_create": (C.c_int, [C.c_int, C.c_int64, C.POINTER(_P)]),
     "afsi_server_destroy": (C.c_int, [_P]),
     "afsi_server_set_pool_columns": (C.c_int, [_P, _P, C.c_int64]),
@@ -306,6 +327,33 @@ def afsi_clenshaw_step_grouped(h, slices, stream=None):
     _check(lib().afsi_clenshaw_step_grouped(h, len(slices), arr, dt, _stream(stream)))
 
 
+def afsi_filter_batched(h, slices, stream=None):
+    """slices: list of (coeffs, degree, X, Y, work) with torch blocks of one dtype, each
+    n x ncols (X, Y and work of a slice share their leading dimension)."""
+    arr = (afsi_slice_filter * max(len(slices), 1))()
+    keep = []
+    dt = R64
+    for i, (coeffs, degree, X, Y, W) in enumerate(slices):
+        c = np.ascontiguousarray(coeffs, dtype=np.float64)
+        if c.size < degree + 1:
+            raise AfsiError(-1, f"slice {i}: {c.size} coefficients for degree {degree}")
+        keep.append(c)
+        bx, by, bw = _blk(X), _blk(Y), _blk(W)
+        if not (bx.ld == by.ld == bw.ld and bx.cols == by.cols == bw.cols
+                and bx.dtype == by.dtype == bw.dtype):
+            raise AfsiError(-1, "a slice's X, Y, work must share shape, ld and dtype")
+        arr[i] = afsi_slice_filter(c.ctypes.data, int(degree), bx.ptr, by.ptr, bw.ptr, bx.cols, bx.ld)
+        dt = bx.dtype
+    _check(lib().afsi_filter_batched(h, len(slices), arr, dt, _stream(stream)))
+
+
+def afsi_block_size(estimate: float, mu: float, n: int) -> int:
+    """p = ceil(mu * estimate) clipped to [1, n] (Section 3.4)."""
+    p = C.c_int64(0)
+    _check(lib().afsi_block_size(float(estimate), float(mu), int(n), C.byref(p)))
+    return p.value
+
+
 def afsi_block_inner(X, Y, G, stream=None):
     _check(lib().afsi_block_inner(_bref(_blk(X)), _bref(_blk(Y)), _bref(_blk(G)), _stream(stream)))
 
@@ -394,6 +442,28 @@ def afsi_solve(h, a: float, b: float, opts: afsi_options, X0, evecs, capacity: i
     res = np.zeros(max(cap, 1))
     r = afsi_result()
     st = lib().afsi_solve(h, a, b, C.byref(opts), _bref(_blk(X0)), _bref(e), cap, _ptr(lam), _ptr(res), C.byref(r), _stream(stream))
+    if st not in (0, -6):
+        _check(st)
+    return st, lam[: r.count].copy(), res[: r.count].copy(), r
+
+
+def afsi_lanczos_options_default(degree: int) -> afsi_lanczos_options:
+    o = afsi_lanczos_options()
+    lib().afsi_lanczos_options_default(C.byref(o), degree)
+    return o
+
+
+def afsi_filtered_lanczos(h, a: float, b: float, opts: afsi_lanczos_options, X0, evecs,
+                          capacity: int | None = None, stream=None):
+    """Returns (status, eigenvalues, residuals, afsi_lanczos_result); E_NOCONV is returned,
+    not raised."""
+    e = _blk(evecs)
+    cap = e.cols if capacity is None else capacity
+    lam = np.zeros(max(cap, 1))
+    res = np.zeros(max(cap, 1))
+    r = afsi_lanczos_result()
+    st = lib().afsi_filtered_lanczos(h, a, b, C.byref(opts), _bref(_blk(X0)), _bref(e), cap, _ptr(lam),
+                                     _ptr(res), C.byref(r), _stream(stream))
     if st not in (0, -6):
         _check(st)
     return st, lam[: r.count].copy(), res[: r.count].copy(), r

@@ -154,7 +154,9 @@ static void run_step(const MatView &mv, int dtype, const void *src, const void *
     if (mv.n == 0 || p == 0) return;
     AFSI_REQUIRE(p < (1LL << 31) && ld < (1LL << 40), "block too wide");
     const int eb = elem_bytes(dtype);
-    const bool vec = (p * eb) % 16 == 0 && (ld * eb) % 16 == 0 && aligned16(src) &&
+    // narrow rows (fewer than 16 vectors, no exact lane mapping): one lane per row
+    const bool narrow = p <= kNarrowMax && p * eb < 16 * 16;
+    const bool vec = !narrow && (p * eb) % 16 == 0 && (ld * eb) % 16 == 0 && aligned16(src) &&
                      aligned16(dst) && (!hx || aligned16(X));
     if (vec) {
         const int p16 = (int)(p * eb / 16);
@@ -619,6 +621,26 @@ int afsi_clenshaw_step_grouped(afsi_matrix_t A, int ngroups, const afsi_slice_bl
     });
 }
 
+int afsi_filter_batched(afsi_matrix_t A, int nslices, const afsi_slice_filter *slices,
+                        int32_t dtype, void *stream) {
+    return guarded([&] {
+        check_matrix(A);
+        DeviceGuard dg(A->device);
+        filter_batched(A, nslices, slices, dtype, as_stream(stream));
+    });
+}
+
+int afsi_block_size(double estimate, double mu, int64_t n, int64_t *p_out) {
+    return guarded([&] {
+        AFSI_REQUIRE(p_out != nullptr, "p_out is NULL");
+        AFSI_REQUIRE(mu > 0.0 && std::isfinite(mu), "mu must be positive (got %g)", mu);
+        AFSI_REQUIRE(n >= 1, "n must be >= 1");
+        AFSI_REQUIRE(std::isfinite(estimate), "estimate is not finite");
+        const double want = std::ceil(mu * estimate);
+        *p_out = want < 1.0 ? 1 : (want >= (double)n ? n : (int64_t)want);
+    });
+}
+
 int afsi_clenshaw_step_batched(afsi_matrix_t A, int ngroups, const afsi_step_group *groups,
                                const afsi_block *X, afsi_block *P0, afsi_block *P1, void *stream) {
     return guarded([&] {
@@ -690,8 +712,9 @@ void batched_step(afsi_matrix_t A, int ngroups, const afsi_step_group *groups, i
     }
 }
 
-void grouped_step(afsi_matrix_t A, int ngroups, const afsi_slice_blocks *slices, int dtype,
-                  hipStream_t s) {
+int grouped_step(afsi_matrix_t A, int ngroups, const afsi_slice_blocks *slices, int dtype,
+                 hipStream_t s, int *kernel_launches) {
+    if (kernel_launches) *kernel_launches = 0;
     AFSI_REQUIRE(ngroups >= 0 && (ngroups == 0 || slices != nullptr), "bad slice list");
     AFSI_REQUIRE(dtype >= AFSI_R64 && dtype <= AFSI_C64, "unknown dtype %d", dtype);
     const int eb = elem_bytes(dtype);
@@ -715,8 +738,9 @@ void grouped_step(afsi_matrix_t A, int ngroups, const afsi_slice_blocks *slices,
         }
         act.push_back(g);
     }
-    if (act.empty() || n == 0) return;
+    if (act.empty() || n == 0) return 0;
     const MatView mv = matrix_view(A, dtype, s);
+    int taken = 0;
     // slices whose rows are whole 16-byte vectors go to the grouped kernel, by width
     std::map<int, std::vector<int>> by_width;
     std::vector<int> rest;
@@ -757,6 +781,10 @@ void grouped_step(afsi_matrix_t A, int ngroups, const afsi_slice_blocks *slices,
             }
             if (!done)
                 for (size_t k = 0; k < cnt; ++k) rest.push_back(gs[g0 + k]);
+            else {
+                taken += (int)cnt;
+                if (kernel_launches) ++*kernel_launches;
+            }
         }
     }
     // widths without an exact lane mapping, and unaligned blocks: one product each
@@ -768,6 +796,49 @@ void grouped_step(afsi_matrix_t A, int ngroups, const afsi_slice_blocks *slices,
                  S.step.alpha != 0.0, S.step.sigma, S.step.tau, S.step.alpha, s);
     }
     AFSI_HIP(hipGetLastError());
+    return taken;
+}
+
+void filter_batched(afsi_matrix_t A, int nslices, const afsi_slice_filter *slices, int dtype,
+                    hipStream_t s) {
+    AFSI_REQUIRE(nslices >= 0 && (nslices == 0 || slices != nullptr), "bad slice list");
+    double l1, l2;
+    map_coeffs(A, l1, l2);
+    int kmax = 0;
+    for (int g = 0; g < nslices; ++g) {
+        const afsi_slice_filter &F = slices[g];
+        AFSI_REQUIRE(F.coeffs != nullptr, "slice %d: coeffs is NULL", g);
+        AFSI_REQUIRE(F.degree >= 1, "slice %d: degree must be >= 1 (got %d)", g, F.degree);
+        AFSI_REQUIRE(F.ncols >= 0 && F.ld >= F.ncols && F.ld >= 1, "slice %d: bad ncols / ld", g);
+        AFSI_REQUIRE(F.ncols == 0 || (F.X && F.Y && F.work), "slice %d: NULL block", g);
+        kmax = std::max(kmax, (int)F.degree);
+    }
+    // per slice: P[0] = X, the last product lands in Y = P[1 + (k-1) % 2] (as filter_apply)
+    std::vector<afsi_slice_blocks> sb(nslices);
+    for (int g = 0; g < nslices; ++g) {
+        const afsi_slice_filter &F = slices[g];
+        void *P[2];
+        P[(F.degree - 1) % 2] = F.Y;
+        P[F.degree % 2] = F.work;
+        sb[g].X = F.X;
+        sb[g].P0 = P[0];
+        sb[g].P1 = P[1];
+        sb[g].ld = F.ld;
+    }
+    for (int st = 0; st < kmax; ++st) {
+        for (int g = 0; g < nslices; ++g) {
+            const afsi_slice_filter &F = slices[g];
+            afsi_step_group &G = sb[g].step;
+            std::memset(&G, 0, sizeof G);
+            if (st < F.degree && F.ncols > 0) {
+                step_params(F.coeffs, F.degree, st, l1, l2, &G);
+                G.col0 = 0;
+                G.ncols = F.ncols;
+                G.active = 1;
+            }
+        }
+        grouped_step(A, nslices, sb.data(), dtype, s);
+    }
 }
 
 void gather_cols(int dtype, const void *src, int64_t n, int64_t ld, const int32_t *cols,

@@ -96,11 +96,38 @@ void dispatch_step(const MatView &A, const void *src, const void *X, void *dst, 
     }
 }
 
+template <class Sr, int P>
+void launch_narrow(const MatView &A, const void *src, const void *X, void *dst, int64_t ld,
+                   bool hv, bool hx, double sg, double ta, double al, hipStream_t s) {
+    using vec = typename Sr::vec;
+    using scal = typename Sr::scal;
+    constexpr int U = P <= 2 ? 8 : (P <= 4 ? 4 : 2);
+    const Grid g = xcd_grid(A.n, 256);
+    hipLaunchKernelGGL((clenshaw_step_narrow_kernel<Sr, P, U>), dim3((unsigned)g.grid), dim3(256), 0,
+                       s, (int)A.n, A.rp, A.ci, (const typename Sr::val *)A.val, (const vec *)src,
+                       (const vec *)X, (vec *)dst, ld, (int)hv, (int)hx, (scal)sg, (scal)ta,
+                       (scal)al, g.group, g.nblocks);
+}
+
+template <class Sr>
+void dispatch_narrow(const MatView &A, const void *src, const void *X, void *dst, int p,
+                     int64_t ld, bool hv, bool hx, double sg, double ta, double al, hipStream_t s) {
+    switch (p) {
+#define AFSI_NARROW(P_)                                                                             \
+    case P_: return launch_narrow<Sr, P_>(A, src, X, dst, ld, hv, hx, sg, ta, al, s);
+    AFSI_NARROW(1) AFSI_NARROW(2) AFSI_NARROW(3) AFSI_NARROW(4) AFSI_NARROW(5) AFSI_NARROW(6)
+    AFSI_NARROW(7) AFSI_NARROW(8) AFSI_NARROW(9) AFSI_NARROW(10) AFSI_NARROW(11) AFSI_NARROW(12)
+    AFSI_NARROW(13) AFSI_NARROW(14) AFSI_NARROW(15) AFSI_NARROW(16)
+#undef AFSI_NARROW
+    }
+}
+
 template <class Sr>
 void dispatch_scalar(const MatView &A, const void *src, const void *X, void *dst, int p,
                      int64_t ld, bool hv, bool hx, double sg, double ta, double al, hipStream_t s) {
     using vec = typename Sr::vec;
     using scal = typename Sr::scal;
+    if (p <= kNarrowMax) return dispatch_narrow<Sr>(A, src, X, dst, p, ld, hv, hx, sg, ta, al, s);
     const Grid g = xcd_grid(A.n, 4);
     hipLaunchKernelGGL((clenshaw_step_scalar_kernel<Sr, 4, 4>), dim3((unsigned)g.grid), dim3(256), 0,
                        s, (int)A.n, A.rp, A.ci, (const typename Sr::val *)A.val, (const vec *)src,

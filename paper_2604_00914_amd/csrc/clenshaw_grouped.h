@@ -103,12 +103,9 @@ void launch_grouped(const MatView &A, GroupArgs &args, hipStream_t s) {
 template <class Tr>
 bool dispatch_grouped(const MatView &A, int p16, GroupArgs &args, hipStream_t s) {
 #define AFSI_GROUPED(VN_, L_)                                                                       \
-    if (p16 == (VN_) * (L_)) return launch_grouped<Tr, VN_, L_>(A, args, s), true
-    if (A.stage_near) { AFSI_GROUPED(1, 64); }  // as in dispatch_flags
-    AFSI_GROUPED(2, 64); AFSI_GROUPED(4, 32); AFSI_GROUPED(4, 64); AFSI_GROUPED(3, 64);
-    AFSI_GROUPED(5, 64); AFSI_GROUPED(3, 32); AFSI_GROUPED(5, 32); AFSI_GROUPED(2, 32);
-    AFSI_GROUPED(6, 64); AFSI_GROUPED(8, 64); AFSI_GROUPED(1, 64); AFSI_GROUPED(1, 32);
-    AFSI_GROUPED(3, 16); AFSI_GROUPED(1, 16);
+    if (p16 == (VN_) * (L_)) return launch_grouped<Tr, VN_, L_>(A, args, s), true;
+    if (A.stage_near) { AFSI_GROUPED(1, 64) }  // as in dispatch_flags
+    AFSI_GROUPED_MAPPINGS(AFSI_GROUPED)
 #undef AFSI_GROUPED
     return false;
 }

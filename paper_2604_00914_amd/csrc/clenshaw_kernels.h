@@ -291,6 +291,63 @@ __global__ __launch_bounds__(256) void clenshaw_step_masked_kernel(
     }
 }
 
+// Narrow blocks (p <= 16 elements per row, any alignment): one lane per row, holding
+// all P elements of it, 64 rows per wave.  The row's entries are taken in entry order
+// with U of them fetched together, each contributing P multiply-adds, so every column
+// gets the same bits as from the wider mappings.  A wave's rows are consecutive, so the
+// gathers of neighbouring rows' nearby columns fall on neighbouring addresses.  Used
+// for the bounds estimate's single vectors (P = 1), narrow Krylov blocks and narrow
+// columns views, where a lane group per row would leave most lanes idle.
+template <class Sr, int P, int U>
+__global__ __launch_bounds__(256) void clenshaw_step_narrow_kernel(
+    int n, const int *__restrict__ rp, const int *__restrict__ ci,
+    const typename Sr::val *__restrict__ va, const typename Sr::vec *__restrict__ src,
+    const typename Sr::vec *__restrict__ X, typename Sr::vec *dst, int64_t ld, int has_v,
+    int has_x, typename Sr::scal sigma, typename Sr::scal tau, typename Sr::scal alpha, int group,
+    int nblocks) {
+    using vec = typename Sr::vec;
+    using val = typename Sr::val;
+    const int lb = xcd_block(blockIdx.x, group, nblocks);
+    if (lb < 0) return;
+    const int row = lb * (int)blockDim.x + (int)threadIdx.x;
+    if (row >= n) return;
+    const int start = rp[row], end = rp[row + 1];
+    vec acc[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) acc[j] = Sr::zero();
+    for (int e0 = start; e0 < end; e0 += U) {
+        int c[U];
+        val a[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u < end ? e0 + u : end - 1;
+            c[u] = ci[e];
+            a[u] = va[e];
+        }
+        vec w[U][P];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const vec *rowp = src + (int64_t)c[u] * ld;
+#pragma unroll
+            for (int j = 0; j < P; ++j) w[u][j] = rowp[j];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (e0 + u < end) {
+#pragma unroll
+                for (int j = 0; j < P; ++j) acc[j] = Sr::fma_val(a[u], w[u][j], acc[j]);
+            }
+    }
+    const int64_t base = (int64_t)row * ld;
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+        vec r = clenshaw_combine<Sr>(sigma, tau, acc[j], src[base + j]);
+        if (has_v) r = Sr::sub(r, dst[base + j]);
+        if (has_x) r = Sr::axpy(alpha, X[base + j], r);
+        dst[base + j] = r;
+    }
+}
+
 // Unaligned rows: one wave per row, one element per lane per 64 columns.
 template <class Tr, int VN, int U>
 __global__ __launch_bounds__(256) void clenshaw_step_scalar_kernel(

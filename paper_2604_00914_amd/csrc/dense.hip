@@ -109,14 +109,23 @@ static void chunking(int64_t n, int64_t tiles, int64_t gran, int64_t target_bloc
     if (nchunks < 1) nchunks = 1;
 }
 
+// Partial sums colsq needs for (n, q): nchunks * q doubles.
+static int64_t colsq_partials(int64_t n, int64_t q) {
+    int64_t rows, nchunks;
+    chunking(n, (q + 63) / 64, 4, 1024, rows, nchunks);
+    return nchunks * q;
+}
+
+// colsq with its chunk partials in `ws` (colsq_partials(n, q) doubles, or NULL: the
+// stream's workspace).
 static void colsq(int dtype, const void *V, int64_t ldv, const void *AV, int64_t ldav,
                   const double *d_lambda, int64_t n, int64_t q, bool take_sqrt, double *d_out,
-                  hipStream_t s) {
+                  hipStream_t s, double *ws = nullptr) {
     if (q == 0) return;
     const int64_t ctiles = (q + 63) / 64;
     int64_t rows, nchunks;
     chunking(n, ctiles, 4, 1024, rows, nchunks);
-    double *ws = (double *)workspace(s).dev_reserve(SLOT_PARTIAL, sizeof(double) * nchunks * q);
+    if (!ws) ws = (double *)workspace(s).dev_reserve(SLOT_PARTIAL, sizeof(double) * nchunks * q);
     const bool cplx = dtype == AFSI_C128;
     auto kern = cplx ? colsq_partial_kernel<true> : colsq_partial_kernel<false>;
     hipLaunchKernelGGL(kern, dim3((unsigned)nchunks, (unsigned)ctiles), dim3(256), 0, s,
@@ -132,6 +141,7 @@ void residual_norms_dev(int dtype, const void *V, int64_t ldv, const void *AV, i
                         hipStream_t s) {
     colsq(dtype, V, ldv, AV, ldav, d_lambda, n, q, true, d_norms, s);
 }
+
 
 void column_dots_dev(int dtype, const void *Z, int64_t ldz, const void *Y, int64_t ldy, int64_t n,
                      int64_t q, double *d_out, hipStream_t s) {

@@ -147,6 +147,28 @@ struct BatchArgs {
     double sigma[64], tau[64], alpha[64];
 };
 
+// Lane mappings of the grouped step kernel, in the order they are tried: X(VN, L) is
+// VN 16-byte vectors per lane and L lanes per row, a row of VN * L vectors.  (A
+// matrix with near-diagonal entries tries X(1, 64) first.)
+#define AFSI_GROUPED_MAPPINGS(X)                                                                    \
+    X(2, 64) X(4, 32) X(4, 64) X(3, 64) X(5, 64) X(3, 32) X(5, 32) X(2, 32) X(6, 64) X(8, 64)      \
+    X(1, 64) X(1, 32) X(3, 16) X(1, 16)
+
+// Smallest row width, in 16-byte vectors, of at least p16 that the grouped kernel
+// maps exactly, or -1 if p16 is wider than every mapping.
+inline int64_t grouped_width_at_least(int64_t p16) {
+    int64_t best = -1;
+#define AFSI_GW(VN_, L_)                                                                            \
+    if ((VN_) * (L_) >= p16 && (best < 0 || (VN_) * (L_) < best)) best = (VN_) * (L_);
+    AFSI_GROUPED_MAPPINGS(AFSI_GW)
+#undef AFSI_GW
+    return best;
+}
+
+// Blocks of at most kNarrowMax elements per row that have no exact lane mapping run the
+// one-lane-per-row kernel (the *_scalar entries take it for p <= kNarrowMax).
+constexpr int kNarrowMax = 16;
+
 // Grouped step: up to kGroupedMax slices with their own blocks, one launch.
 constexpr int kGroupedMax = 32;
 struct GroupArgs {
@@ -238,8 +260,13 @@ void gather_cols(int dtype, const void *src, int64_t n, int64_t ld, const int32_
                  int64_t count, void *dst, int64_t ldd, hipStream_t s);
 void batched_step(afsi_matrix_t A, int ngroups, const afsi_step_group *groups, int dtype,
                   const void *X, void *P0, void *P1, int64_t ptot, int64_t ld, hipStream_t s);
-void grouped_step(afsi_matrix_t A, int ngroups, const afsi_slice_blocks *slices, int dtype,
-                  hipStream_t s);
+// Returns how many of the active slices the grouped kernel took (the others, with a
+// width that has no exact lane mapping or unaligned blocks, ran one product each).
+// kernel_launches (optional) receives the number of grouped-kernel launches.
+int grouped_step(afsi_matrix_t A, int ngroups, const afsi_slice_blocks *slices, int dtype,
+                 hipStream_t s, int *kernel_launches = nullptr);
+void filter_batched(afsi_matrix_t A, int nslices, const afsi_slice_filter *slices, int dtype,
+                    hipStream_t s);
 
 // ---------------------------------------------------------------- host linear algebra
 // host_cholesky_inverse, host_eigh: host_linalg.h (built without HIP, with OpenMP).

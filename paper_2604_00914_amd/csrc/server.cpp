@@ -7,17 +7,23 @@
 // request owning pool columns [c0, c0 + w) owns the contiguous n x w region at
 // element offset n * c0 of every buffer (row-major, leading dimension w), so the CSR
 // matrix and every request's subspace stay resident and every request's rows are
-// contiguous.  Each pool has its own HIP stream and host thread.  A pool thread
-// repeats rounds:
-//   * one grouped Clenshaw product (afsi_clenshaw_step_grouped semantics) for every
-//     request that is filtering, whatever product index each one is at - one launch
-//     per width for all of them;
-//   * the dense phases (Cholesky QR, Rayleigh-Ritz, residuals, locking - the steps
-//     of Algorithm 4) of every request whose filter just finished.
-// Requests that arrive while others run are admitted as soon as columns and bytes
-// free up; independent matrices progress concurrently on their own streams.  A
-// request's column arithmetic does not depend on its neighbours, so its results
-// are bit-identical alone and in a mix.
+// contiguous.  Each pool has two host threads, each with its own HIP stream:
+//   * the product thread repeats rounds of one grouped Clenshaw product
+//     (afsi_clenshaw_step_grouped semantics) for every request that is filtering,
+//     whatever product index each one is at - one launch per width for all of them;
+//     a request's filtered width is padded up to a width the grouped kernel maps
+//     exactly (within its slot; the extra columns are discarded), so slices keep
+//     sharing launches after some of their pairs have locked;
+//   * the dense thread takes the requests whose filter has finished, one at a time,
+//     and runs their dense phases (Cholesky QR, Rayleigh-Ritz, residuals, locking -
+//     the steps of Algorithm 4; also the start block's orthonormalisation), so one
+//     request's host factorisations never hold up the other slices' products.
+// A request moves between the two streams through its own HIP event (recorded on
+// the stream that wrote its slot last, waited on by the other).  Requests that
+// arrive while others run are admitted as soon as columns and bytes free up;
+// independent matrices progress concurrently on their own streams.  A request's
+// column arithmetic does not depend on its neighbours, so its results are
+// bit-identical alone and in a mix.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -37,9 +43,16 @@ namespace afsi {
 namespace srv {
 
 enum { Q_QUEUED = 0, Q_RUNNING = 1, Q_DONE = 2, Q_FAILED = 3 };
-enum { PH_INIT = 0, PH_FILTER = 1, PH_DENSE = 2 };
+// PH_INIT and PH_DENSE wait for (or run in) the dense thread; PH_FILTER is the product
+// thread's; PH_GONE: finished, to be dropped by the product thread.
+enum { PH_INIT = 0, PH_FILTER = 1, PH_DENSE = 2, PH_GONE = 3 };
 
 struct Pool;
+
+// Dense threads per pool: the dense phases of that many requests run concurrently,
+// each on its own stream (they are host-latency bound: small factorisations between
+// device steps).
+constexpr int kDenseWorkers = 2;
 
 struct Request {
     int64_t id = 0;
@@ -69,6 +82,9 @@ struct Session {
     int k_cur = 1, step = 0, phase = PH_INIT;
     int64_t n_check_prev = 0;
     std::vector<int> degrees;
+    hipEvent_t ev = nullptr;    // last write to the slot, on the stream that made it
+    bool ev_recorded = false;   // ev holds a record to wait for
+    bool in_dense = false;      // owned by the dense thread (queued or running)
 };
 
 struct Server;
@@ -80,7 +96,13 @@ struct Pool {
     int64_t n = 0, cap = 0, E = 1;
     void *B[3] = {nullptr, nullptr, nullptr};  // FP64: active block, filter output / Q, work / AV
     void *F[3] = {nullptr, nullptr, nullptr};  // filter precision (mixed form only)
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;                  // products (product thread)
+    hipStream_t dstream[kDenseWorkers] = {};       // dense phases, one per dense thread
+    std::thread dense[kDenseWorkers];
+    std::deque<Session *> dense_q;  // sessions handed to the dense thread (under S->mu)
+    std::deque<Session *> back_q;   // sessions it has handed back (under S->mu)
+    bool dense_stop = false;
+    int64_t in_dense = 0;
     std::vector<uint8_t> used;  // per column
     std::list<Session> sessions;
     std::deque<Session> incoming;
@@ -174,6 +196,7 @@ struct Server {
     int live_threads = 0;
     bool stopping = false;
     int64_t launches = 0, launch_groups = 0;
+    int64_t kernel_launches = 0, kernel_slices = 0;  // grouped kernel launches / slices they took
     std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
     double now() const {
         return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -263,9 +286,13 @@ void try_admit(Server *S) {
                 if (np->mixed())
                     for (auto &b : np->F) b = S->arena.alloc(np->fblk);
                 AFSI_HIP(hipStreamCreateWithFlags(&np->stream, hipStreamNonBlocking));
+                for (auto &d : np->dstream) AFSI_HIP(hipStreamCreateWithFlags(&d, hipStreamNonBlocking));
             } catch (...) {
                 for (auto &b : np->B) S->arena.release(b, np->blk), b = nullptr;
                 for (auto &b : np->F) S->arena.release(b, np->fblk), b = nullptr;
+                if (np->stream) (void)hipStreamDestroy(np->stream);
+                for (auto d : np->dstream)
+                    if (d) (void)hipStreamDestroy(d);
                 fail_queued(S, r, AFSI_E_NOMEM, "device allocation of the request's pool failed");
                 it = S->queue.erase(it);
                 continue;
@@ -334,12 +361,12 @@ void finish(Pool *P, Session &s, int status, const std::string &err) {
 }
 
 // Start block from the request's seed, orthonormalised (Algorithm 4, initialisation).
-void init_session(Pool *P, Session &s) {
+void init_session(Pool *P, Session &s, hipStream_t st) {
     Request *r = s.r;
     const int comp = is_complex(P->dt) ? 2 : 1;
     void *B0 = slot_ptr(P, P->B[0], s, P->dt);
-    launch_fill_normal((double *)B0, P->n, r->p, s.cap, comp, r->seed, P->stream);
-    orthonormalize_dev(P->dt, B0, slot_ptr(P, P->B[1], s, P->dt), P->n, r->p, s.cap, P->stream,
+    launch_fill_normal((double *)B0, P->n, r->p, s.cap, comp, r->seed, st);
+    orthonormalize_dev(P->dt, B0, slot_ptr(P, P->B[1], s, P->dt), P->n, r->p, s.cap, st,
                        nullptr);
     s.coeffs.resize(r->opts.kmax + 1);
     filter_coefficients(r->A->lmin, r->A->lmax, r->a, r->b, r->opts.kmax, r->opts.damping,
@@ -359,13 +386,13 @@ void init_session(Pool *P, Session &s) {
     }
 }
 
-void start_filter(Pool *P, Session &s) {
+void start_filter(Pool *P, Session &s, hipStream_t st) {
     s.phase = PH_FILTER;
     s.step = 0;
     if (P->mixed()) {
         afsi_block src{slot_ptr(P, P->B[0], s, P->dt), P->n, s.p_act, s.cap, P->dt};
         afsi_block dst{slot_ptr(P, P->F[0], s, P->fdt), P->n, s.p_act, s.cap, P->fdt};
-        launch_convert(src, dst, P->stream);
+        launch_convert(src, dst, st);
     }
 }
 
@@ -381,7 +408,7 @@ void publish(Pool *P, Request *r, int iterations, int64_t spmv, int64_t locked) 
 }
 
 // One pass of the dense steps after a filter; says whether the request goes on.
-int dense_phase(Pool *P, Session &s) {
+int dense_phase(Pool *P, Session &s, hipStream_t st) {
     Request *r = s.r;
     const int dt = P->dt;
     const int64_t n = P->n, ld = s.cap, pa = s.p_act;
@@ -390,7 +417,7 @@ int dense_phase(Pool *P, Session &s) {
     if (P->mixed()) {
         afsi_block src{slot_ptr(P, P->F[outi], s, P->fdt), n, pa, ld, P->fdt};
         afsi_block dst{slot_ptr(P, P->B[1], s, dt), n, pa, ld, dt};
-        launch_convert(src, dst, P->stream);
+        launch_convert(src, dst, st);
         q = slot_ptr(P, P->B[1], s, dt);
         w = slot_ptr(P, P->B[2], s, dt);
     } else {
@@ -400,14 +427,14 @@ int dense_phase(Pool *P, Session &s) {
     void *v = slot_ptr(P, P->B[0], s, dt);
     s.degrees.push_back(s.k_cur);
     publish(P, r, 1, (int64_t)s.k_cur * pa, 0);
-    if (r->n_lock > 0) project_out_dev(dt, r->evecs, r->p, r->n_lock, q, ld, n, pa, P->stream);
+    if (r->n_lock > 0) project_out_dev(dt, r->evecs, r->p, r->n_lock, q, ld, n, pa, st);
     double maxn2 = 0.0;
-    orthonormalize_dev(dt, q, w, n, pa, ld, P->stream, &maxn2);
+    orthonormalize_dev(dt, q, w, n, pa, ld, st, &maxn2);
     if (r->opts.damping != AFSI_DAMP_NONE && maxn2 > 16.0)
         AFSI_FAIL(AFSI_E_BOUNDS, "filtered block grew by %.3g: spectral bounds do not enclose A",
                   std::sqrt(maxn2));
     std::vector<double> ritz(pa), res(pa);
-    rayleigh_ritz_dev(r->A, dt, q, v, w, n, pa, ld, ritz.data(), P->stream);
+    rayleigh_ritz_dev(r->A, dt, q, v, w, n, pa, ld, ritz.data(), st);
     publish(P, r, 0, pa, 0);
     std::vector<uint8_t> I(pa), lock(pa);
     int64_t e = 0;
@@ -419,7 +446,7 @@ int dense_phase(Pool *P, Session &s) {
         if (r->opts.adaptive)
             s.k_cur = select_degree(ritz.data(), pa, e, s.coeffs.data(), r->opts.kmax, s.l1, s.l2,
                                     r->opts.tau_a);
-        residual_norms_host(dt, v, ld, w, ld, ritz.data(), n, pa, res.data(), P->stream);
+        residual_norms_host(dt, v, ld, w, ld, ritz.data(), n, pa, res.data(), st);
         int done = 0;
         lock_select(ritz.data(), pa, res.data(), I.data(), r->a, r->b, s.tau_abs, r->n_lock,
                     &s.n_check_prev, lock.data(), &done);
@@ -432,12 +459,12 @@ int dense_phase(Pool *P, Session &s) {
                 r->res.push_back(res[j]);
             }
             gather_cols(dt, v, n, ld, lk.data(), (int64_t)lk.size(), col_ptr(r->evecs, r->n_lock, dt),
-                        r->p, P->stream);
+                        r->p, st);
             if (!keep.empty()) {
-                gather_cols(dt, v, n, ld, keep.data(), (int64_t)keep.size(), w, ld, P->stream);
+                gather_cols(dt, v, n, ld, keep.data(), (int64_t)keep.size(), w, ld, st);
                 const int eb = elem_bytes(dt);
                 AFSI_HIP(hipMemcpy2DAsync(v, ld * eb, w, ld * eb, keep.size() * eb, n,
-                                          hipMemcpyDeviceToDevice, P->stream));
+                                          hipMemcpyDeviceToDevice, st));
             }
             publish(P, r, 0, 0, (int64_t)lk.size());
             s.p_act -= (int64_t)lk.size();
@@ -445,11 +472,11 @@ int dense_phase(Pool *P, Session &s) {
         if (done) return DP_CONVERGED;
     }
     if (r->iterations >= r->opts.max_iter) return DP_LIMIT;
-    start_filter(P, s);
+    start_filter(P, s, st);
     return DP_CONTINUE;
 }
 
-void sort_results(Pool *P, const Session &s, Request *r) {
+void sort_results(Pool *P, const Session &s, Request *r, hipStream_t st) {
     if (r->n_lock < 2) return;
     std::vector<int32_t> order(r->n_lock);
     std::iota(order.begin(), order.end(), 0);
@@ -462,10 +489,10 @@ void sort_results(Pool *P, const Session &s, Request *r) {
     // buffer (n x s.cap, free once the dense phase is over; n_lock <= p <= s.cap)
     const int dt = P->dt, eb = elem_bytes(dt);
     void *tmp = slot_ptr(P, P->B[2], s, dt);
-    gather_cols(dt, r->evecs, P->n, r->p, order.data(), r->n_lock, tmp, s.cap, P->stream);
+    gather_cols(dt, r->evecs, P->n, r->p, order.data(), r->n_lock, tmp, s.cap, st);
     AFSI_HIP(hipMemcpy2DAsync(r->evecs, r->p * eb, tmp, s.cap * eb, r->n_lock * eb, P->n,
-                              hipMemcpyDeviceToDevice, P->stream));
-    AFSI_HIP(hipStreamSynchronize(P->stream));
+                              hipMemcpyDeviceToDevice, st));
+    AFSI_HIP(hipStreamSynchronize(st));
 }
 
 // Stream of a pool that has left S->pools (so no request can be admitted to it): wait
@@ -474,29 +501,141 @@ void sort_results(Pool *P, const Session &s, Request *r) {
 void retire_pool_stream(Pool *P) {
     (void)hipStreamSynchronize(P->stream);
     (void)hipStreamDestroy(P->stream);
+    for (hipStream_t st : P->dstream) {
+        (void)hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
+    }
 }
+
+// Filtered width of a session: its active columns rounded up to whole 16-byte vectors,
+// then up to the nearest width the grouped kernel maps exactly if that fits the slot.
+int64_t filter_width(const Pool *P, const Session &s) {
+    const int64_t nc = round_up(s.p_act, P->E);
+    const int eb = elem_bytes(P->fdt);
+    const int64_t w16 = grouped_width_at_least(nc * eb / 16);
+    if (w16 > 0 && w16 * 16 / eb <= s.cap) return w16 * 16 / eb;
+    return nc;
+}
+
+// A dense thread of a pool: start blocks (PH_INIT) and the dense phases after each
+// filter (PH_DENSE), one session at a time, on the thread's own stream.
+void dense_thread(Pool *P, int worker) {
+    Server *S = P->S;
+    (void)hipSetDevice(S->device);
+    hipStream_t st = P->dstream[worker];
+    for (;;) {
+        Session *sp = nullptr;
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            S->cv.wait(lk, [&] { return !P->dense_q.empty() || P->dense_stop; });
+            if (P->dense_q.empty()) return;  // dense_stop and nothing left
+            sp = P->dense_q.front();
+            P->dense_q.pop_front();
+            if (S->stopping) {  // hand it back untouched: the product thread fails it
+                P->back_q.push_back(sp);
+                S->cv.notify_all();
+                continue;
+            }
+        }
+        Session &s = *sp;
+        try {
+            if (s.ev_recorded) AFSI_HIP(hipStreamWaitEvent(st, s.ev, 0));
+            if (s.phase == PH_INIT) {
+                init_session(P, s, st);
+                start_filter(P, s, st);
+            } else {
+                const int outcome = dense_phase(P, s, st);
+                if (outcome != DP_CONTINUE) {
+                    sort_results(P, s, s.r, st);
+                    finish(P, s, outcome == DP_CONVERGED ? AFSI_OK : AFSI_E_NOCONV, "");
+                    s.phase = PH_GONE;
+                }
+            }
+            if (s.phase != PH_GONE) {
+                AFSI_HIP(hipEventRecord(s.ev, st));
+                s.ev_recorded = true;
+            }
+        } catch (const Error &e) {
+            (void)hipStreamSynchronize(st);
+            finish(P, s, e.status, afsi_last_error());
+            s.phase = PH_GONE;
+        } catch (const std::exception &e) {
+            (void)hipStreamSynchronize(st);
+            finish(P, s, AFSI_E_NOMEM, e.what());
+            s.phase = PH_GONE;
+        }
+        std::lock_guard<std::mutex> lk(S->mu);
+        P->back_q.push_back(sp);
+        S->cv.notify_all();
+    }
+}
+
+// Launches the product thread keeps queued ahead of the device: it waits for launch
+// i - kAhead before issuing launch i, so requests that arrive or come back from their
+// dense phase join the next rounds instead of queueing behind a whole filter.
+constexpr int kAhead = 3;
 
 void pool_thread(Pool *P) {
     Server *S = P->S;
     (void)hipSetDevice(S->device);
+    hipEvent_t ahead[kAhead] = {};
+    for (auto &e : ahead)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            e = nullptr;
+        }
+    int64_t rounds = 0;
+    for (int w = 0; w < kDenseWorkers; ++w) P->dense[w] = std::thread(dense_thread, P, w);
     std::vector<afsi_slice_blocks> groups;
     std::vector<Session *> filt;
+    std::vector<Session *> fresh, back;
     for (;;) {
+        fresh.clear();
+        back.clear();
         {
             std::unique_lock<std::mutex> lk(S->mu);
-            while (!P->incoming.empty()) {
-                P->sessions.push_back(std::move(P->incoming.front()));
-                P->incoming.pop_front();
+            for (;;) {
+                while (!P->incoming.empty()) {
+                    P->sessions.push_back(std::move(P->incoming.front()));
+                    P->incoming.pop_front();
+                    fresh.push_back(&P->sessions.back());
+                }
+                for (Session *sp : P->back_q) {
+                    sp->in_dense = false;
+                    back.push_back(sp);
+                }
+                P->in_dense -= (int64_t)P->back_q.size();
+                P->back_q.clear();
+                bool filtering = false;
+                for (auto &x : P->sessions) filtering |= !x.in_dense && x.phase == PH_FILTER;
+                const bool idle = P->sessions.empty() && P->in_dense == 0;
+                if (filtering || !fresh.empty() || !back.empty() || idle || S->stopping) break;
+                S->cv.wait(lk);
             }
-            if (P->sessions.empty() || S->stopping) {
-                for (auto &s : P->sessions) {
-                    s.r->state = Q_FAILED;
-                    s.r->status = AFSI_E_INVALID;
-                    s.r->error = "server stopped";
+            const bool gone = std::all_of(P->sessions.begin(), P->sessions.end(),
+                                          [](const Session &x) { return x.phase == PH_GONE; });
+            if ((gone && P->in_dense == 0) || S->stopping) {
+                P->dense_stop = true;
+                S->cv.notify_all();
+                lk.unlock();
+                for (auto &th : P->dense) th.join();  // they return once the queue is empty
+                lk.lock();
+                for (Session *sp : P->back_q) sp->in_dense = false;
+                P->back_q.clear();
+                P->in_dense = 0;
+                for (auto &x : P->sessions) {
+                    if (x.phase == PH_GONE) continue;
+                    x.r->state = Q_FAILED;
+                    x.r->status = AFSI_E_INVALID;
+                    x.r->error = "server stopped";
                 }
                 S->pools.erase(std::make_pair(P->A, P->fdt));
                 lk.unlock();
                 retire_pool_stream(P);
+                for (auto &x : P->sessions)
+                    if (x.ev) (void)hipEventDestroy(x.ev);
+                for (auto e : ahead)
+                    if (e) (void)hipEventDestroy(e);
                 lk.lock();
                 for (auto b : P->B) S->arena.release(b, P->blk);
                 for (auto b : P->F) S->arena.release(b, P->fblk);
@@ -508,78 +647,94 @@ void pool_thread(Pool *P) {
                 return;
             }
         }
-        // sessions that need initialisation, one batched product, then dense phases
-        std::vector<std::list<Session>::iterator> done;
-        for (auto it = P->sessions.begin(); it != P->sessions.end(); ++it) {
-            if (it->phase != PH_INIT) continue;
-            try {
-                init_session(P, *it);
-                start_filter(P, *it);
-            } catch (const Error &e) {
-                it->r->error = afsi_last_error();
-                finish(P, *it, e.status, it->r->error);
-                done.push_back(it);
-            } catch (const std::exception &e) {
-                finish(P, *it, AFSI_E_NOMEM, e.what());
-                done.push_back(it);
+        // finished sessions leave; new ones go to the dense thread for their start block
+        P->sessions.remove_if([](Session &x) {
+            if (x.phase != PH_GONE || x.in_dense) return false;
+            if (x.ev) (void)hipEventDestroy(x.ev);
+            return true;
+        });
+        std::vector<Session *> to_dense;
+        for (Session *sp : fresh) {
+            if (hipEventCreateWithFlags(&sp->ev, hipEventDisableTiming) != hipSuccess) {
+                (void)hipGetLastError();
+                sp->ev = nullptr;
+                finish(P, *sp, AFSI_E_HIP, "hipEventCreate failed");
+                sp->phase = PH_GONE;
+                continue;
             }
+            to_dense.push_back(sp);
         }
-        for (auto it : done) P->sessions.erase(it);
-        done.clear();
+        // sessions back from the dense thread with a filter to run: the product stream
+        // waits for their dense work
+        for (Session *sp : back)
+            if (sp->phase == PH_FILTER && sp->ev_recorded &&
+                hipStreamWaitEvent(P->stream, sp->ev, 0) != hipSuccess) {
+                (void)hipGetLastError();
+                for (hipStream_t d : P->dstream) (void)hipStreamSynchronize(d);
+            }
         filt.clear();
         groups.clear();
-        for (auto &s : P->sessions)
-            if (s.phase == PH_FILTER) {
+        for (auto &x : P->sessions)
+            if (!x.in_dense && x.phase == PH_FILTER) {
                 afsi_slice_blocks g{};
-                step_params(s.coeffs.data(), s.k_cur, s.step, s.l1, s.l2, &g.step);
+                step_params(x.coeffs.data(), x.k_cur, x.step, x.l1, x.l2, &g.step);
                 g.step.col0 = 0;
-                g.step.ncols = round_up(s.p_act, P->E);
+                g.step.ncols = filter_width(P, x);
                 g.step.active = 1;
                 void **buf = P->mixed() ? P->F : P->B;
-                g.X = slot_ptr(P, buf[0], s, P->fdt);
-                g.P0 = slot_ptr(P, buf[1], s, P->fdt);
-                g.P1 = slot_ptr(P, buf[2], s, P->fdt);
-                g.ld = s.cap;
+                g.X = slot_ptr(P, buf[0], x, P->fdt);
+                g.P0 = slot_ptr(P, buf[1], x, P->fdt);
+                g.P1 = slot_ptr(P, buf[2], x, P->fdt);
+                g.ld = x.cap;
                 groups.push_back(g);
-                filt.push_back(&s);
+                filt.push_back(&x);
             }
         try {
             if (!groups.empty()) {
-                grouped_step(P->A, (int)groups.size(), groups.data(), P->fdt, P->stream);
+                hipEvent_t &slot = ahead[rounds % kAhead];
+                if (rounds >= kAhead && slot) AFSI_HIP(hipEventSynchronize(slot));
+                int klaunch = 0;
+                const int taken = grouped_step(P->A, (int)groups.size(), groups.data(), P->fdt,
+                                               P->stream, &klaunch);
+                if (slot) AFSI_HIP(hipEventRecord(slot, P->stream));
+                ++rounds;
                 std::lock_guard<std::mutex> lk(S->mu);
                 ++S->launches;
                 S->launch_groups += (int64_t)groups.size();
+                S->kernel_launches += klaunch;
+                S->kernel_slices += taken;
             }
-        } catch (const Error &e) {
-            const std::string msg = afsi_last_error();
-            for (auto *s : filt) s->phase = -1, finish(P, *s, e.status, msg);
-            P->sessions.remove_if([](const Session &s) { return s.phase == -1; });
-            continue;
-        } catch (const std::exception &e) {
-            for (auto *s : filt) s->phase = -1, finish(P, *s, AFSI_E_NOMEM, e.what());
-            P->sessions.remove_if([](const Session &s) { return s.phase == -1; });
-            continue;
-        }
-        for (auto *s : filt)
-            if (++s->step == s->k_cur) s->phase = PH_DENSE;
-        for (auto it = P->sessions.begin(); it != P->sessions.end(); ++it) {
-            if (it->phase != PH_DENSE) continue;
-            try {
-                const int outcome = dense_phase(P, *it);
-                if (outcome != DP_CONTINUE) {
-                    sort_results(P, *it, it->r);
-                    finish(P, *it, outcome == DP_CONVERGED ? AFSI_OK : AFSI_E_NOCONV, "");
-                    done.push_back(it);
+            for (auto *x : filt)
+                if (++x->step == x->k_cur) {
+                    x->phase = PH_DENSE;
+                    AFSI_HIP(hipEventRecord(x->ev, P->stream));
+                    x->ev_recorded = true;
+                    to_dense.push_back(x);
                 }
-            } catch (const Error &e) {
-                finish(P, *it, e.status, afsi_last_error());
-                done.push_back(it);
-            } catch (const std::exception &e) {
-                finish(P, *it, AFSI_E_NOMEM, e.what());
-                done.push_back(it);
-            }
+        } catch (const Error &e) {
+            // none of filt has reached the dense thread yet
+            const std::string msg = afsi_last_error();
+            (void)hipStreamSynchronize(P->stream);
+            for (auto *x : filt) x->phase = PH_GONE, finish(P, *x, e.status, msg);
+            to_dense.erase(std::remove_if(to_dense.begin(), to_dense.end(),
+                                          [](Session *x) { return x->phase == PH_GONE; }),
+                           to_dense.end());
+        } catch (const std::exception &e) {
+            (void)hipStreamSynchronize(P->stream);
+            for (auto *x : filt) x->phase = PH_GONE, finish(P, *x, AFSI_E_NOMEM, e.what());
+            to_dense.erase(std::remove_if(to_dense.begin(), to_dense.end(),
+                                          [](Session *x) { return x->phase == PH_GONE; }),
+                           to_dense.end());
         }
-        for (auto it : done) P->sessions.erase(it);
+        if (!to_dense.empty()) {
+            std::lock_guard<std::mutex> lk(S->mu);
+            for (Session *sp : to_dense) {
+                sp->in_dense = true;
+                P->dense_q.push_back(sp);
+            }
+            P->in_dense += (int64_t)to_dense.size();
+            S->cv.notify_all();
+        }
     }
 }
 
@@ -775,6 +930,8 @@ int afsi_server_get_stats(afsi_server_t S, afsi_server_stats *st) {
         st->pools = (int64_t)S->pools.size();
         st->batched_launches = S->launches;
         st->batched_groups = S->launch_groups;
+        st->kernel_launches = S->kernel_launches;
+        st->kernel_slices = S->kernel_slices;
         st->now = S->now();
     });
 }

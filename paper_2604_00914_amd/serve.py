@@ -44,6 +44,12 @@ class StreamReport:
             "eigenpairs_per_s": round(pairs / max(self.wall_s, 1e-9), 2),
             "slices_per_batched_launch": round(self.stats.get("batched_groups", 0) /
                                                max(self.stats.get("batched_launches", 1), 1), 3),
+            # slice products that shared a grouped-kernel launch, per launch, and the share
+            # of all slice products that went through the grouped kernel
+            "slices_per_grouped_kernel": round(self.stats.get("kernel_slices", 0) /
+                                               max(self.stats.get("kernel_launches", 1), 1), 3),
+            "grouped_kernel_share": round(self.stats.get("kernel_slices", 0) /
+                                          max(self.stats.get("batched_groups", 1), 1), 3),
         }
 
 

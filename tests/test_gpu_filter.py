@@ -400,6 +400,7 @@ def test_full_size_batched_slices_sampled_columns(stagger):
     l1, l2 = co.affine_map(lo, hi)
     ivs = slice_intervals(A.n, 0.5 * (lo + hi), G, 50)
     coeffs = [afsi.afsi_filter_coefficients(lo, hi, a, b, k, "jackson") for a, b in ivs]
+    ref_coeffs = [co.filter_coefficients(lo, hi, a, b, k, "jackson") for a, b in ivs]
     X0 = start_block(A.n, G * cols, seed=0)
     M = afsi.Matrix(A, bounds=(lo, hi))
     X = to_dev(X0)
@@ -417,8 +418,110 @@ def test_full_size_batched_slices_sampled_columns(stagger):
     t.cuda.empty_cache()
     M.close()
     for j, g in enumerate(range(G)):
-        ref = clenshaw_filter(A, np.ascontiguousarray(X0[:, pick[j]:pick[j] + 1]), coeffs[g], l1, l2)
+        ref = clenshaw_filter(A, np.ascontiguousarray(X0[:, pick[j]:pick[j] + 1]), ref_coeffs[g], l1, l2)
         _check(got[:, j:j + 1], ref, F64_TOL)
+
+
+@pytest.mark.parametrize("single", [False, True])
+@pytest.mark.parametrize("stagger", [0, 1])
+def test_full_size_grouped_slices_sampled_columns(stagger, single):
+    # the server's slice step (the grouped kernel) at full size: 16 slices x 96 columns of
+    # the 100^3 matrix, degree 120, every slice in its own n x 96 blocks with its own
+    # coefficients; stagger 1 puts odd slices one step behind, so one launch mixes source
+    # blocks and V / X flags; one sampled column per slice against the oracle's filter
+    from workloads.stream import slice_intervals
+
+    t = torch()
+    A, (lo, hi), _, cfg = build_config("lap3d_pot_100")
+    k, G, cols = cfg.degree, 16, 96
+    l1, l2 = co.affine_map(lo, hi)
+    ivs = slice_intervals(A.n, 0.5 * (lo + hi), G, 50)
+    coeffs = [afsi.afsi_filter_coefficients(lo, hi, a, b, k, "jackson") for a, b in ivs]
+    ref_coeffs = [co.filter_coefficients(lo, hi, a, b, k, "jackson") for a, b in ivs]
+    dt = t.float32 if single else t.float64
+    M = afsi.Matrix(A, bounds=(lo, hi))
+    pick, cols0, blocks = [], [], []
+    for g in range(G):
+        X0 = start_block(A.n, cols, seed=100 + g)
+        c = (7 * g) % cols
+        pick.append(c)
+        cols0.append(np.ascontiguousarray(X0[:, c:c + 1]))
+        X = t.from_numpy(X0).to(DEV).to(dt)
+        blocks.append((X, t.zeros_like(X), t.zeros_like(X)))
+        del X0
+    for step in range(k + stagger):
+        sl = []
+        for g in range(G):
+            s_g = step - stagger * (g % 2)
+            if 0 <= s_g < k:
+                sl.append((afsi.afsi_clenshaw_step_params(coeffs[g], k, s_g, l1, l2, ncols=cols), *blocks[g]))
+        afsi.afsi_clenshaw_step_grouped(M.handle, sl)
+    t.cuda.synchronize()
+    got = [blocks[g][1 + (k - 1) % 2][:, pick[g]].cpu().numpy().astype(np.float64) for g in range(G)]
+    del blocks
+    t.cuda.empty_cache()
+    M.close()
+    for g in range(G):
+        ref = clenshaw_filter(A, cols0[g], ref_coeffs[g], l1, l2)
+        _check(got[g][:, None], ref, f32_tol(k) if single else F64_TOL)
+
+
+@pytest.mark.parametrize("cplx,single", [(False, False), (False, True), (True, False), (True, True)])
+def test_filter_batched_equals_single_filters(cplx, single):
+    # the whole-filter slice call: slices of different widths (grouped-kernel widths and
+    # widths that fall back to one product each), degrees and intervals; every slice's Y
+    # bit-identical to afsi_filter_block on that slice alone and within tolerance of the
+    # oracle's filter
+    t = torch()
+    if cplx:
+        A = tight_binding_3d_periodic(8, seed=3)
+        lmin, lmax = -7.5, 7.5
+        shift = -5.0
+    else:
+        A = laplacian_3d_dirichlet(10, 2.0, seed=4)
+        lmin, lmax = 0.0, 14.0
+        shift = 0.0
+    dt = _tdt(cplx, single)
+    M = afsi.Matrix(A, bounds=(lmin, lmax))
+    spec = [(64, 72, 9, (5.0, 5.3)), (64, 64, 4, (7.0, 7.4)), (96, 96, 11, (2.0, 2.4)),
+            (10, 12, 6, (4.0, 4.6)), (128, 128, 1, (8.0, 9.0))]
+    slices, X0s, cs = [], [], []
+    for g, (nc, ld, k, (a, b)) in enumerate(spec):
+        X0 = start_block(A.n, nc, seed=40 + g, complex_=cplx)
+        X0s.append(X0)
+        c = afsi.afsi_filter_coefficients(lmin, lmax, a + shift, b + shift, k, "jackson")
+        cs.append(c)
+        bufs = [t.zeros((A.n, ld), dtype=dt, device=DEV) for _ in range(3)]
+        bufs[0][:, :nc] = t.from_numpy(X0).to(DEV).to(dt)
+        slices.append((c, k, *(b_[:, :nc] for b_ in bufs)))
+    afsi.afsi_filter_batched(M.handle, slices)
+    t.cuda.synchronize()
+    for g, (nc, ld, k, (a, b)) in enumerate(spec):
+        Y = slices[g][3].cpu().numpy()
+        Xs = t.from_numpy(X0s[g]).to(DEV).to(dt)
+        Ys, Ws = t.empty_like(Xs), t.empty_like(Xs)
+        afsi.afsi_filter_block(M.handle, cs[g], k, Xs, Ys, Ws)
+        t.cuda.synchronize()
+        assert np.array_equal(Y, Ys.cpu().numpy()), g
+        ref = oracle_filter(A, X0s[g], lmin, lmax, a + shift, b + shift, k)
+        _check(Y.astype(np.complex128 if cplx else np.float64), ref, f32_tol(k) if single else F64_TOL)
+    M.close()
+
+
+def test_filter_batched_errors():
+    t = torch()
+    A = laplacian_3d_dirichlet(6, 1.0, seed=2)
+    M = afsi.Matrix(A, bounds=(0.0, 14.0))
+    c = afsi.afsi_filter_coefficients(0.0, 14.0, 3.0, 4.0, 5)
+    X = to_dev(start_block(A.n, 32, seed=1))
+    Y, W = t.zeros_like(X), t.zeros_like(X)
+    with pytest.raises(afsi.AfsiError):  # degree 0
+        afsi.afsi_filter_batched(M.handle, [(c, 0, X, Y, W)])
+    with pytest.raises(afsi.AfsiError):  # two slices write one block
+        afsi.afsi_filter_batched(M.handle, [(c, 5, X, Y, W), (c, 5, to_dev(start_block(A.n, 32, seed=2)), Y,
+                                                             t.zeros_like(X))])
+    afsi.afsi_filter_batched(M.handle, [])  # nothing to do
+    M.close()
 
 
 # (ncols, ld, degree, interval, first step): widths with an exact lane mapping (the

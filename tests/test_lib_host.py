@@ -197,3 +197,17 @@ def test_invalid_csr_is_rejected_before_device_use():
         afsi.afsi_matrix_create_csr(0, 2, 3, rp, np.array([0, 2, 1]), np.ones(3), afsi.R64)  # out of range
     with pytest.raises(afsi.AfsiError):
         afsi.afsi_matrix_create_csr(0, 2, 3, np.array([0, 2, 4]), np.array([0, 1, 1]), np.ones(3), afsi.R64)
+
+
+def test_block_size_from_count():
+    # Section 3.4: p = ceil(mu * e~), Section 4's mu = 1.8; clipped to [1, n]
+    assert afsi.afsi_block_size(196.59, 1.8, 19683) == 354   # 353.862 rounds up
+    assert afsi.afsi_block_size(200.0, 1.8, 10 ** 6) == 360  # exact product, no round-up
+    assert afsi.afsi_block_size(40.7, 1.8, 4096) == 74
+    assert afsi.afsi_block_size(-3.0, 1.8, 100) == 1
+    assert afsi.afsi_block_size(0.0, 1.8, 100) == 1
+    assert afsi.afsi_block_size(1e9, 1.8, 4096) == 4096
+    for bad in ((10.0, 0.0, 100), (10.0, -1.0, 100), (float("nan"), 1.8, 100), (10.0, 1.8, 0)):
+        with pytest.raises(afsi.AfsiError) as e:
+            afsi.afsi_block_size(*bad)
+        assert e.value.status == -1
