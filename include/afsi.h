@@ -306,6 +306,20 @@ int afsi_rayleigh_ritz(afsi_matrix_t A, const afsi_block *Q, afsi_block *V, afsi
 int afsi_residual_norms(const afsi_block *V, const afsi_block *AV, const double *lambda,
                         double *norms_out, void *stream);
 
+/*
+ * afsi_residual_norms for callers that cannot allocate device or pinned host memory
+ * (code that must not call hipMalloc, such as a tight serving loop or a caller that
+ * forbids allocation).  Same arguments, results and errors as afsi_residual_norms; its
+ * device work uses a fixed array of 2^17 doubles (1 MiB) that the library keeps on every
+ * device it runs on until the process ends, holding the eigenvalues, the chunk partials
+ * and the norms: 2 q + (row chunks) * q doubles, at most about 2 q + 65536 + 64 ceil(q/64),
+ * so any n with q <= 8192 fits.  Larger shapes get AFSI_E_INVALID.  lambda and norms_out
+ * are ordinary host memory, copied on `stream`; synchronises `stream`.  Calls that
+ * overlap on one device share the array and race: serialise them.
+ */
+int afsi_residual_norms_noalloc(const afsi_block *V, const afsi_block *AV, const double *lambda,
+                                double *norms_out, void *stream);
+
 /* dst = src converted (R64 <-> R32, C128 <-> C64, or same type copy); same shape. */
 int afsi_convert_block(const afsi_block *src, afsi_block *dst, void *stream);
 

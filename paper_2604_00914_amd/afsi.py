@@ -121,6 +121,7 @@ _SIGS = {
     "afsi_orthonormalize": (C.c_int, [_BP, _BP, _BP, _P]),
     "afsi_rayleigh_ritz": (C.c_int, [_P, _BP, _BP, _BP, _P, _P]),
     "afsi_residual_norms": (C.c_int, [_BP, _BP, _P, _P, _P]),
+    "afsi_residual_norms_noalloc": (C.c_int, [_BP, _BP, _P, _P, _P]),
     "afsi_convert_block": (C.c_int, [_BP, _BP, _P]),
     "afsi_gather_columns": (C.c_int, [_BP, _P, C.c_int64, _BP, _P]),
     "afsi_select_degree": (C.c_int, [_P, C.c_int64, C.c_int64, _P, C.c_int, C.c_double, C.c_double, C.c_double, C.POINTER(C.c_int)]),
@@ -379,6 +380,15 @@ def afsi_residual_norms(V, AV, lam, stream=None) -> np.ndarray:
     lam = _np(lam, np.float64)
     out = np.empty(v.cols, dtype=np.float64)
     _check(lib().afsi_residual_norms(_bref(v), _bref(_blk(AV)), _ptr(lam), _ptr(out), _stream(stream)))
+    return out
+
+
+def afsi_residual_norms_noalloc(V, AV, lam, stream=None) -> np.ndarray:
+    v = _blk(V)
+    lam = _np(lam, np.float64)
+    out = np.empty(v.cols, dtype=np.float64)
+    _check(lib().afsi_residual_norms_noalloc(_bref(v), _bref(_blk(AV)), _ptr(lam), _ptr(out),
+                                             _stream(stream)))
     return out
 
 

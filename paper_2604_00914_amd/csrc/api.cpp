@@ -944,6 +944,20 @@ int afsi_residual_norms(const afsi_block *V, const afsi_block *AV, const double 
     });
 }
 
+int afsi_residual_norms_noalloc(const afsi_block *V, const afsi_block *AV, const double *lambda,
+                                double *norms_out, void *stream) {
+    return guarded([&] {
+        check_block(V, "V");
+        check_block(AV, "AV");
+        check_fp64(V, "V");
+        AFSI_REQUIRE(V->rows == AV->rows && V->cols == AV->cols && V->dtype == AV->dtype,
+                     "V and AV shapes differ");
+        AFSI_REQUIRE(V->cols == 0 || (lambda && norms_out), "NULL lambda / norms_out");
+        residual_norms_noalloc(V->dtype, V->ptr, V->ld, AV->ptr, AV->ld, lambda, V->rows, V->cols,
+                               norms_out, as_stream(stream));
+    });
+}
+
 int afsi_convert_block(const afsi_block *src, afsi_block *dst, void *stream) {
     return guarded([&] {
         check_block(src, "src");

@@ -142,6 +142,50 @@ void residual_norms_dev(int dtype, const void *V, int64_t ldv, const void *AV, i
     colsq(dtype, V, ldv, AV, ldav, d_lambda, n, q, true, d_norms, s);
 }
 
+// ---------------------------------------------------------------- allocation-free residuals
+//
+// Device memory of afsi_residual_norms_noalloc: the eigenvalues, the chunk partials and
+// the norms of one call, kNoallocDoubles doubles in all.  Each device holds its own copy
+// of this array from the library's load until the process ends; host code must address
+// it through the pointer hipGetSymbolAddress returns on that device, never by its name.
+constexpr int64_t kNoallocDoubles = int64_t(1) << 17;  // 1 MiB
+static __device__ __align__(256) double scratch[kNoallocDoubles];
+
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[256];  // per device ordinal, set on first use
+
+static double *scratch_ptr(int dev) {
+    AFSI_REQUIRE(dev >= 0 && dev < 256, "device ordinal %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        AFSI_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        AFSI_REQUIRE(p != nullptr, "no device address for the residual scratch");
+        g_scratch_ptr[dev] = (double *)p;
+    }
+    return g_scratch_ptr[dev];
+}
+
+int64_t residual_noalloc_need(int64_t n, int64_t q) { return 2 * q + colsq_partials(n, q); }
+int64_t residual_noalloc_capacity() { return kNoallocDoubles; }
+
+void residual_norms_noalloc(int dtype, const void *V, int64_t ldv, const void *AV, int64_t ldav,
+                            const double *lambda, int64_t n, int64_t q, double *out,
+                            hipStream_t s) {
+    if (q == 0) return;
+    const int64_t need = residual_noalloc_need(n, q);
+    AFSI_REQUIRE(need <= kNoallocDoubles,
+                 "%lld columns of %lld rows need %lld doubles of scratch; the allocation-free "
+                 "residual call holds %lld", (long long)q, (long long)n, (long long)need,
+                 (long long)kNoallocDoubles);
+    int dev = 0;
+    AFSI_HIP(hipGetDevice(&dev));
+    double *d_lam = scratch_ptr(dev), *d_out = d_lam + q, *ws = d_lam + 2 * q;
+    AFSI_HIP(hipMemcpyAsync(d_lam, lambda, sizeof(double) * q, hipMemcpyHostToDevice, s));
+    colsq(dtype, V, ldv, AV, ldav, d_lam, n, q, true, d_out, s, ws);
+    AFSI_HIP(hipMemcpyAsync(out, d_out, sizeof(double) * q, hipMemcpyDeviceToHost, s));
+    AFSI_HIP(hipStreamSynchronize(s));
+}
 
 void column_dots_dev(int dtype, const void *Z, int64_t ldz, const void *Y, int64_t ldy, int64_t n,
                      int64_t q, double *d_out, hipStream_t s) {

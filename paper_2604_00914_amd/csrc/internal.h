@@ -223,6 +223,13 @@ void gemm_c128(const double *X, int64_t ldx, const double *M, int64_t ldm, int64
 void residual_norms_dev(int dtype, const void *V, int64_t ldv, const void *AV, int64_t ldav,
                         const double *d_lambda, int64_t n, int64_t q, double *d_norms,
                         hipStream_t s);
+// As residual_norms_host, with every device buffer in the library's fixed per-device
+// scratch array (no allocation); rejects shapes that need more than it holds.
+void residual_norms_noalloc(int dtype, const void *V, int64_t ldv, const void *AV, int64_t ldav,
+                            const double *lambda, int64_t n, int64_t q, double *out,
+                            hipStream_t s);
+int64_t residual_noalloc_need(int64_t n, int64_t q);  // doubles of scratch for (n, q)
+int64_t residual_noalloc_capacity();                   // doubles the scratch holds
 // d_out[j] = Re sum_i conj(Z[i, j]) Y[i, j], device output (q doubles).  R64 or C128.
 void column_dots_dev(int dtype, const void *Z, int64_t ldz, const void *Y, int64_t ldy, int64_t n,
                      int64_t q, double *d_out, hipStream_t s);
