@@ -79,7 +79,7 @@ def main():
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=0)
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run three plain device copies of one block (counter calibration)")
     ap.add_argument("--cpu-baseline-sweep", default=None, metavar="OUT",
@@ -322,7 +322,9 @@ def main():
 
     if not args.no_solve:
         out["solve"] = solve_rates(afsi, torch, dev)
+        out["lanczos"] = lanczos_rates(afsi, torch, dev)
         out["eigencount"] = eigencount_rates(afsi, torch, dev)
+        out["irregular"] = irregular_record(afsi, torch, dev)
     if not args.no_serve:
         out["serve"] = serve_rates(afsi, M, args.serve_requests)
 
@@ -722,9 +724,18 @@ def eigencount_rates(afsi, torch, dev, probes=64):
         dt = time.perf_counter() - t0
         rec = {"n": A.n, "degree": cfg.degree, "probes": probes, "estimate": round(est, 2),
                "std_error": round(float(np.std(per, ddof=1) / np.sqrt(per.size)), 2),
-               "block_size": int(np.ceil(1.8 * est)), "configured_p": cfg.p, "ms": round(dt * 1e3, 2)}
+               "block_size": afsi.afsi_block_size(est, 1.8, A.n), "configured_p": cfg.p,
+               "ms": round(dt * 1e3, 2)}
         if name != "lap3d_pot_100":
             rec["exact_count"] = int(_window_fixture(name).size)
+        else:
+            # the other setup step: Lanczos bounds (40 steps, one vector) against Gershgorin
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            lo, hi = afsi.afsi_estimate_spectral_bounds(M.handle, 40, 7)
+            rec["bounds_estimate"] = {"steps": 40, "lmin": round(lo, 6), "lmax": round(hi, 6),
+                                      "gershgorin": [round(lmin, 6), round(lmax, 6)],
+                                      "ms": round((time.perf_counter() - t0) * 1e3, 2)}
         log(f"eigencount {name}: {rec}")
         out[name] = rec
         del Z, Y, W
@@ -733,59 +744,204 @@ def eigencount_rates(afsi, torch, dev, probes=64):
     return out
 
 
-def serve_rates(afsi, M_slices, num):
+# (workload, block s, basis m, degree): filtered thick-restart block Lanczos settings
+LANCZOS_RUNS = [("lap2d_64", 8, 128, 60), ("lap3d_pot_27", 32, 512, 120), ("lap3d_pot_27", 32, 512, 200)]
+
+
+def lanczos_rates(afsi, torch, dev, seeds=(0, 1, 2, 3, 4)):
+    """Eigenpairs/s of the filtered thick-restart block Lanczos (Jackson filter of a fixed
+    degree, tau_c = 1e-10) on the converging workloads, from resident start blocks, mean
+    over start-block seeds 0-4; a run counts its pairs only with the fixture's exact count
+    and every eigenvalue within 1e-10 ||A||.  The subspace-iteration figures of the same
+    workloads are in the solve record."""
+    from workloads import build_config, start_block
+
+    out = {}
+    for name, s_blk, m, deg in LANCZOS_RUNS:
+        A, (lmin, lmax), (a, b), cfg = build_config(name)
+        exact = _window_fixture(name)
+        normA = max(abs(lmin), abs(lmax))
+        M = afsi.Matrix(A, device=0, bounds=(lmin, lmax))
+        E = torch.zeros((A.n, 2 * exact.size + m), dtype=torch.float64, device=dev)
+        o = afsi.afsi_lanczos_options_default(deg)
+        o.block, o.basis, o.max_cycles = s_blk, m, 300
+        runs = []
+        for i, sd in enumerate((seeds[0],) + tuple(seeds)):
+            X0 = torch.from_numpy(start_block(A.n, s_blk, seed=sd)).to(dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, lam, res, r = afsi.afsi_filtered_lanczos(M.handle, a, b, o, X0, E)
+            dt = time.perf_counter() - t0
+            if i == 0:
+                continue  # untimed: first-use allocations
+            ok = st == 0 and lam.size == exact.size and np.max(np.abs(lam - exact)) <= 1e-10 * normA
+            runs.append({"seed": sd, "seconds": round(dt, 4), "eigenpairs": int(lam.size) if ok else 0,
+                         "cycles": r.cycles, "filter_columns": r.filter_columns})
+        rate = [x["eigenpairs"] / x["seconds"] for x in runs]
+        rec = {"n": A.n, "block": s_blk, "basis": m, "degree": deg, "eigenvalues": int(exact.size),
+               "eigenpairs_per_s": round(float(np.mean(rate)), 2),
+               "seconds": round(float(np.mean([x["seconds"] for x in runs])), 4),
+               "cycles": round(float(np.mean([x["cycles"] for x in runs])), 1),
+               "filter_products_x_columns": int(np.mean([x["filter_columns"] for x in runs])) * deg,
+               "all_correct": all(x["eigenpairs"] == exact.size for x in runs)}
+        log(f"lanczos {name} s={s_blk} m={m} k={deg}: {rec}")
+        out[f"{name}_s{s_blk}_m{m}_k{deg}"] = rec
+        M.close()
+        del E
+        torch.cuda.empty_cache()
+    return out
+
+
+def irregular_record(afsi, torch, dev, products=8):
+    """The irregular matrix (n = 2e6, ~24 nnz/row, half of each row's columns uniform at
+    random) at its full block width p = 640 in FP32: steady Clenshaw products (HIP events),
+    against the compulsory bytes and the gather-inclusive model (every off-band entry
+    gathers its source row from HBM).  The block is N(0,1) drawn on the device."""
+    from workloads import build_config
+
+    A, (lmin, lmax), (a, b), cfg = build_config("rand_2m")
+    M = afsi.Matrix(A, device=0, bounds=(lmin, lmax))
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(0)
+    X = torch.randn((A.n, cfg.p), dtype=torch.float32, device=dev, generator=gen)
+    Y, W = torch.empty_like(X), torch.empty_like(X)
+    coeffs = afsi.afsi_filter_coefficients(lmin, lmax, a, b, products, cfg.damping)
+    afsi.afsi_filter_block_profiled(M.handle, coeffs, products, X, Y, W)  # warm-up
+    ms, kind = afsi.afsi_filter_block_profiled(M.handle, coeffs, products, X, Y, W)
+    steady = float(np.mean(ms[2:][kind[2:] == 3]))
+    pb = A.n * cfg.p * 4
+    a_bytes = A.nnz * 8 + 4 * (A.n + 1)
+    compulsory = a_bytes + 4 * pb
+    # off-band entries (|col - row| > 64) gather a whole row from HBM each
+    rp, ci = A.row_ptr, A.col
+    rows = np.repeat(np.arange(A.n), np.diff(rp))
+    far = int(np.count_nonzero(np.abs(ci.astype(np.int64) - rows) > 64))
+    gathered = compulsory + far * cfg.p * 4
+    rec = {"n": A.n, "nnz": A.nnz, "p": cfg.p, "dtype": "f32", "steady_product_us": round(steady * 1e3, 1),
+           "compulsory_bytes": compulsory, "compulsory_gbs": round(compulsory / (steady * 1e-3) / 1e9, 1),
+           "far_entries": far, "gather_inclusive_bytes": gathered,
+           "gather_inclusive_gbs": round(gathered / (steady * 1e-3) / 1e9, 1)}
+    rec["compulsory_frac"] = round(rec["compulsory_gbs"] / HBM_PEAK_GBS, 4)
+    log(f"irregular rand_2m fp32: {rec}")
+    M.close()
+    del X, Y, W
+    torch.cuda.empty_cache()
+    return rec
+
+
+def serve_rates(afsi, M_slices, num, loads=(0.5, 0.8, 0.95)):
     """p50/p99 latency and throughput of the continuous-batching server.
 
-    (a) the serving mix: Poisson arrivals, half spectrum slices of the 100^3 matrix
-        (p = 96, degree 120, batched per round), half independent 3D Laplacian +
-        potential matrices (n log-uniform in [1e4, 1e6], p in {32..256}, degree in
-        [40, 200]); a fixed budget of 2 iterations per request bounds the run;
-    (b) a converging stream of 2D Laplacian window requests (40 eigenpairs each),
-        for eigenpairs/s.  Both in FP64 and in the mixed form.
+    (a) the serving mix (the literal stream): half spectrum slices of the 100^3 matrix
+        (16 slices, p = 96, degree 120, slices of one matrix share grouped launches),
+        half independent 3D Laplacian + potential matrices (n log-uniform in [1e4, 1e6],
+        p in {32..256}, degree in [40, 200]); a fixed budget of 2 iterations per
+        request.  The capacity is measured first (all `num` requests submitted at once,
+        requests finished per second); then `num` Poisson arrivals at each offered load
+        (a fraction of that capacity) give the latency percentiles.  FP64 and mixed.
+    (b) a converging stream at equal accuracy (tau_c = 1e-6 in both forms, plus FP64 at
+        1e-10): 2D Laplacian window requests (40 eigenpairs, fixed Jackson degree 60)
+        and 27^3 Laplacian + potential requests (196 eigenpairs, the paper's adaptive
+        mode); eigenpairs/s counts a request's pairs only when its count equals the
+        fixture's and every eigenvalue is within 1e-5 ||A|| (1e-10 ||A|| at tau_c 1e-10).
     """
     from paper_2604_00914_amd import serve
+    from tests.golden_util import lap2d_window, lap3d27_window
     from workloads import build_config, laplacian_3d_dirichlet
     from workloads.stream import serving_stream
 
-    reqs = serving_stream(num, rate_hz=8.0, seed=0)
+    reqs = serving_stream(num, rate_hz=1.0, seed=0)   # arrivals rescaled per load below
+    base = np.array([r.arrival for r in reqs])
     mats = {}
     for r in reqs:
         if r.kind == "matrix" and r.grid not in mats:
             mats[r.grid] = afsi.Matrix(laplacian_3d_dirichlet(r.grid, 2.0, seed=r.seed), bounds=(0.0, 14.0))
-    out = {"mix": {"requests": num, "rate_hz": 8.0, "max_iter": 2,
-                   "slices": sum(r.kind == "slice" for r in reqs)}}
-    for form in ("fp64", "mixed"):
+    out = {"mix": {"requests": num, "max_iter": 2, "slices": sum(r.kind == "slice" for r in reqs),
+                   "loads": list(loads)}}
+
+    def jobs_for(form, arrivals):
         jobs = []
-        for r in reqs:
+        for r, t in zip(reqs, arrivals):
             o = afsi.afsi_options_default(r.degree)
             o.max_iter = 2
             if form == "mixed":
                 o.filter_dtype, o.tau_c = afsi.R32, 1e-6
             M = M_slices if r.kind == "slice" else mats[r.grid]
-            jobs.append((r.arrival, M, r.a, r.b, r.p, o, r.seed, r.kind))
+            jobs.append((float(t), M, r.a, r.b, r.p, o, r.seed, r.kind))
+        return jobs
+
+    def run(jobs):
         with serve.Server(hbm_budget_bytes=200 << 30) as S:
             S.set_pool_columns(M_slices, 16 * 96)
-            rep = serve.run_stream(S, jobs)
-        out["mix"][form] = rep.summary()
-        log(f"serve mix {form}: {out['mix'][form]}")
-    A, (lmin, lmax), (a, b), cfg = build_config("lap2d_64")
-    M1 = afsi.Matrix(A, bounds=(lmin, lmax))
-    rng = np.random.default_rng(1)
-    arrivals = np.cumsum(rng.exponential(1.0 / 40.0, size=16))
-    out["converging"] = {"workload": cfg.name, "requests": 16, "rate_hz": 40.0}
+            return serve.run_stream(S, jobs).summary()
+
     for form in ("fp64", "mixed"):
-        o = afsi.afsi_options_default(cfg.degree)
-        if form == "mixed":
-            o.filter_dtype, o.tau_c = afsi.R32, 1e-6
-        jobs = [(float(t), M1, a, b, cfg.p, o, 500 + i, i) for i, t in enumerate(arrivals)]
+        burst = run(jobs_for(form, np.zeros(num)))
+        cap = burst["throughput_req_per_s"]
+        rec = {"capacity_req_per_s": cap, "burst": burst}
+        for load in loads:
+            s = run(jobs_for(form, base / (load * cap)))
+            s["offered_req_per_s"] = round(load * cap, 3)
+            rec[f"load_{load}"] = s
+            log(f"serve mix {form} load {load}: {s}")
+        out["mix"][form] = rec
+
+    # (b) converging stream
+    specs = []
+    A1, (lo1, hi1), (a1, b1), cfg1 = build_config("lap2d_64")
+    A2, (lo2, hi2), (a2, b2), cfg2 = build_config("lap3d_pot_27")
+    M1, M2 = afsi.Matrix(A1, bounds=(lo1, hi1)), afsi.Matrix(A2, bounds=(lo2, hi2))
+    ref = {"lap2d_64": lap2d_window(), "lap3d_pot_27": lap3d27_window()}
+    norm = {"lap2d_64": max(abs(lo1), abs(hi1)), "lap3d_pot_27": max(abs(lo2), abs(hi2))}
+    k1 = paper_initial_degree(lo2, hi2, a2, b2)
+    rng = np.random.default_rng(1)
+    arrivals = np.cumsum(rng.exponential(1.0 / 40.0, size=24))
+    for i, t in enumerate(arrivals):
+        if i % 3 == 2:
+            specs.append((float(t), "lap3d_pot_27", M2, a2, b2, cfg2.p, math.ceil(2.5 * k1), True))
+        else:
+            specs.append((float(t), "lap2d_64", M1, a1, b1, cfg1.p, cfg1.degree, False))
+    out["converging"] = {"requests": len(specs), "rate_hz": 40.0,
+                         "workloads": {"lap2d_64": "fixed Jackson degree 60, p = 64",
+                                       "lap3d_pot_27": f"adaptive (Lanczos m = 0.5, k1 = {k1}, "
+                                                       f"kmax = {math.ceil(2.5 * k1)}), p = {cfg2.p}"}}
+    for form, tau_c in (("fp64", 1e-10), ("fp64", 1e-6), ("mixed", 1e-6)):
+        jobs = []
+        for i, (t, name, M, a, b, p, kmax, adaptive) in enumerate(specs):
+            o = afsi.afsi_options_default(kmax)
+            o.tau_c, o.max_iter = tau_c, 1500
+            if adaptive:
+                o.adaptive, o.damping = 1, afsi.DAMP_LANCZOS
+            if form == "mixed":
+                o.filter_dtype = afsi.R32
+            jobs.append((t, M, a, b, p, o, 500 + i, name))
         with serve.Server(hbm_budget_bytes=64 << 30) as S:
-            S.set_pool_columns(M1, 16 * cfg.p)
+            S.set_pool_columns(M1, 8 * cfg1.p)
+            S.set_pool_columns(M2, 4 * cfg2.p)
             rep = serve.run_stream(S, jobs)
-        out["converging"][form] = rep.summary()
-        log(f"serve converging {form}: {out['converging'][form]}")
+        s = rep.summary()
+        tol = 1e-10 if tau_c <= 1e-10 else 1e-5
+        good = 0
+        wrong = 0
+        for c in rep.completed:
+            r = ref[c.tag]
+            ok = c.eigenvalues.size == r.size and np.max(np.abs(c.eigenvalues - r)) <= tol * norm[c.tag]
+            good += r.size if ok else 0
+            wrong += 0 if ok else 1
+        s["correct_eigenpairs_per_s"] = round(good / max(rep.wall_s, 1e-9), 2)
+        s["requests_not_exact"] = wrong
+        s["tau_c"] = tau_c
+        key = form if tau_c > 1e-10 else "fp64_tau1e-10"
+        out["converging"][key] = s
+        log(f"serve converging {key}: {s}")
+    c = out["converging"]
+    if c["fp64"]["correct_eigenpairs_per_s"] > 0:
+        c["mixed_vs_fp64_equal_tau"] = round(c["mixed"]["correct_eigenpairs_per_s"] /
+                                             c["fp64"]["correct_eigenpairs_per_s"], 3)
     for M in mats.values():
         M.close()
     M1.close()
+    M2.close()
     return out
 
 

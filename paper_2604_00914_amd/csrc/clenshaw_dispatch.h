@@ -77,6 +77,7 @@ void dispatch_flags(const MatView &A, const void *src, const void *X, void *dst,
     AFSI_EXACT(3, 32); AFSI_EXACT(5, 32); AFSI_EXACT(2, 32);
     AFSI_EXACT(6, 64); AFSI_EXACT(8, 64); AFSI_EXACT(1, 64); AFSI_EXACT(1, 32);
     AFSI_EXACT(3, 16); AFSI_EXACT(1, 16);
+    AFSI_EXACT(3, 8);  // 24 vectors: the FP32 slice width p = 96
 #undef AFSI_EXACT
     if (p16 <= 64) return launch_masked<Tr, 1, HV, HX>(A, src, X, dst, ldv, p16, sg, ta, al, s);
     if (p16 <= 128) return launch_masked<Tr, 2, HV, HX>(A, src, X, dst, ldv, p16, sg, ta, al, s);

@@ -152,7 +152,7 @@ struct BatchArgs {
 // matrix with near-diagonal entries tries X(1, 64) first.)
 #define AFSI_GROUPED_MAPPINGS(X)                                                                    \
     X(2, 64) X(4, 32) X(4, 64) X(3, 64) X(5, 64) X(3, 32) X(5, 32) X(2, 32) X(6, 64) X(8, 64)      \
-    X(1, 64) X(1, 32) X(3, 16) X(1, 16)
+    X(1, 64) X(1, 32) X(3, 16) X(1, 16) X(3, 8)
 
 // Smallest row width, in 16-byte vectors, of at least p16 that the grouped kernel
 // maps exactly, or -1 if p16 is wider than every mapping.

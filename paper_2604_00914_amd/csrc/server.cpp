@@ -615,6 +615,9 @@ void pool_thread(Pool *P) {
             const bool gone = std::all_of(P->sessions.begin(), P->sessions.end(),
                                           [](const Session &x) { return x.phase == PH_GONE; });
             if ((gone && P->in_dense == 0) || S->stopping) {
+                // leave the pool table first, under the lock that admission holds: no
+                // request can be admitted into this pool from here on
+                S->pools.erase(std::make_pair(P->A, P->fdt));
                 P->dense_stop = true;
                 S->cv.notify_all();
                 lk.unlock();
@@ -629,7 +632,6 @@ void pool_thread(Pool *P) {
                     x.r->status = AFSI_E_INVALID;
                     x.r->error = "server stopped";
                 }
-                S->pools.erase(std::make_pair(P->A, P->fdt));
                 lk.unlock();
                 retire_pool_stream(P);
                 for (auto &x : P->sessions)

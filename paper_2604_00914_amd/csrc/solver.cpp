@@ -39,21 +39,6 @@ void gather(int dtype, const void *src, int64_t n, int64_t ld, const std::vector
     gather_cols(dtype, src, n, ld, cols.data(), (int64_t)cols.size(), dst, ldd, s);
 }
 
-// splitmix64 (Steele, Lea, Flood 2014) and Box-Muller normals for the Lanczos start vector
-struct SplitMix {
-    uint64_t x;
-    uint64_t next() {
-        uint64_t z = (x += 0x9E3779B97F4A7C15ULL);
-        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
-        z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
-        return z ^ (z >> 31);
-    }
-    double uniform() { return ((next() >> 11) + 0.5) * (1.0 / 9007199254740992.0); }
-    double normal() {
-        const double u1 = uniform(), u2 = uniform();
-        return std::sqrt(-2.0 * std::log(u1)) * std::cos(6.283185307179586 * u2);
-    }
-};
 
 }  // namespace
 
@@ -264,19 +249,16 @@ int afsi_estimate_spectral_bounds(afsi_matrix_t A, int steps, uint64_t seed, voi
         const int64_t ld = m + 1;
         DevBuf Q((size_t)n * ld * comp * sizeof(double));
         DevBuf h((size_t)(ld + 2) * comp * sizeof(double));
-        std::vector<double> q0((size_t)n * comp);
-        SplitMix rng{seed};
-        double nrm = 0.0;
-        for (auto &v : q0) {
-            v = rng.normal();
-            nrm += v * v;
-        }
-        nrm = std::sqrt(nrm);
-        for (auto &v : q0) v /= nrm;
-        AFSI_HIP(hipMemcpy2DAsync(Q.p, ld * comp * sizeof(double), q0.data(), comp * sizeof(double),
-                                  comp * sizeof(double), n, hipMemcpyHostToDevice, s));
         std::vector<double> alpha, beta, hh((size_t)(ld + 2) * comp);
         double *Qd = (double *)Q.p, *hd = (double *)h.p;
+        // start vector: N(0,1) entries from the device's counter-based generator keyed by
+        // `seed` (written in place in the strided first column), normalised
+        launch_fill_normal(Qd, n, 1, ld, comp, seed, s);
+        inner_dev(dt, Qd, ld, Qd, ld, n, 1, 1, hd, 1, s);
+        AFSI_HIP(hipMemcpyAsync(hh.data(), hd, comp * sizeof(double), hipMemcpyDeviceToHost, s));
+        AFSI_HIP(hipStreamSynchronize(s));
+        AFSI_REQUIRE(hh[0] > 0.0, "start vector of the bounds estimate is zero");
+        launch_scale(Qd, n, ld, comp, 1.0 / std::sqrt(hh[0]), s);
         double last_beta = 0.0;
         for (int j = 0; j < m; ++j) {
             double *qj = Qd + (size_t)j * comp, *w = Qd + (size_t)(j + 1) * comp;

@@ -140,8 +140,8 @@ def run_stream(server: Server, jobs, timeout_s: float = 3600.0) -> StreamReport:
         delay = arrival - (time.perf_counter() - t0)
         if delay > 0:
             time.sleep(delay)
-        rid = server.submit(matrix, a, b, p, opts, seed)
-        with lock:
+        with lock:  # the collector reads a request's tag under this lock
+            rid = server.submit(matrix, a, b, p, opts, seed)
             tags[rid] = tag
     submitted.set()
     th.join(timeout_s)

@@ -149,3 +149,20 @@ def test_timed_stream_reports_latency():
     assert s["requests"] == 9 and s["p99_latency_s"] >= s["p50_latency_s"] > 0
     for M in mats:
         M.close()
+
+
+def test_requests_arriving_as_pools_drain_all_finish():
+    # requests of a few small matrices arriving while earlier ones finish: pools empty,
+    # retire and are created again; every request must finish (a request admitted into
+    # a pool that is retiring must not be lost)
+    mats = [afsi.Matrix(laplacian_3d_dirichlet(N, 2.0, seed=N), bounds=(0.0, 14.0)) for N in (8, 9, 10)]
+    jobs = []
+    for i in range(36):
+        jobs.append((0.004 * i, mats[i % 3], 6.9, 7.1, 32, _opts(20 + i, max_iter=1), 300 + i, i))
+    with serve.Server(hbm_budget_bytes=4 << 30) as S:
+        rep = serve.run_stream(S, jobs, timeout_s=120.0)
+        st = S.stats()
+    assert len(rep.completed) == 36 and st["running"] == 0 and st["queued"] == 0
+    assert all(c.info.get("state") == 2 for c in rep.completed)
+    for M in mats:
+        M.close()
