@@ -94,6 +94,9 @@ def main():
     ap.add_argument("--sensitivity", default=None, metavar="OUT",
                     help="only run the parameter-sensitivity solves (damping exponent m, "
                          "tau_a, C_r adaptive vs fixed); one JSON line per solve into OUT")
+    ap.add_argument("--irregular", default=None, metavar="OUT",
+                    help="only measure the steady product of the irregular n = 2e6 matrix at "
+                         "p = 640 FP32; one JSON line into OUT")
     ap.add_argument("--gather-cost", default=None, metavar="OUT",
                     help="only measure the steady product on the 100^3 matrix restricted to "
                          "its diagonal, +-1, +-N and all neighbours; one JSON line per case into OUT")
@@ -124,6 +127,11 @@ def main():
         return
     if args.sensitivity:
         sensitivity(afsi, torch, dev, args.sensitivity)
+        return
+    if args.irregular:
+        rec = irregular_record(afsi, torch, dev)
+        with open(args.irregular, "w") as fh:
+            fh.write(json.dumps(rec) + "\n")
         return
     if args.slices:
         rec = batched_record(afsi, torch, dev)

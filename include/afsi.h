@@ -97,6 +97,20 @@ int afsi_matrix_create_csr(int device, int64_t n, int64_t nnz, const int64_t *ro
                            const int32_t *col_idx, const void *vals, int32_t val_dtype,
                            afsi_matrix_t *out);
 int afsi_matrix_destroy(afsi_matrix_t A);
+
+/*
+ * Column blocks of the dense operand (the first loop of Section 3.3.1's MaSpMM, over
+ * column blocks of width T_k, each reused while every row of A passes over it).  With
+ * `bytes` > 0 every product of a row-major block wider than `bytes` runs as one pass of
+ * A per column block of that many bytes, so the gathered rows of one block stay in the
+ * device's memory-side cache; results are bit-identical to whole-row passes.  0 = whole
+ * rows in one pass, the default (whole rows measured as fast or faster on the
+ * workloads here: blocks re-read A once per block).  `bytes` must be 0 or a width the
+ * library's grouped kernel maps (64, 128, 256, 384, 512, 768, 1024, ... bytes;
+ * AFSI_E_INVALID otherwise).
+ */
+int afsi_matrix_set_column_block(afsi_matrix_t A, int64_t bytes);
+int afsi_matrix_get_column_block(afsi_matrix_t A, int64_t *bytes);
 /* n, nnz, value dtype (AFSI_R64 or AFSI_C128), device ordinal. Any output may be NULL. */
 int afsi_matrix_info(afsi_matrix_t A, int64_t *n, int64_t *nnz, int32_t *dtype, int32_t *device);
 

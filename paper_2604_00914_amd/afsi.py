@@ -102,6 +102,8 @@ _SIGS = {
     "afsi_device_count": (C.c_int, []),
     "afsi_matrix_create_csr": (C.c_int, [C.c_int, C.c_int64, C.c_int64, _P, _P, _P, C.c_int32, C.POINTER(_P)]),
     "afsi_matrix_destroy": (C.c_int, [_P]),
+    "afsi_matrix_set_column_block": (C.c_int, [_P, C.c_int64]),
+    "afsi_matrix_get_column_block": (C.c_int, [_P, _I64P]),
     "afsi_matrix_info": (C.c_int, [_P, _I64P, _I64P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "afsi_set_spectral_bounds": (C.c_int, [_P, C.c_double, C.c_double]),
     "afsi_get_spectral_bounds": (C.c_int, [_P, _DP, _DP]),
@@ -264,6 +266,16 @@ def afsi_estimate_spectral_bounds(h, steps: int = 40, seed: int = 0, stream=None
     lo, hi = C.c_double(), C.c_double()
     _check(lib().afsi_estimate_spectral_bounds(h, steps, seed, _stream(stream), C.byref(lo), C.byref(hi)))
     return lo.value, hi.value
+
+
+def afsi_matrix_set_column_block(h, nbytes: int):
+    _check(lib().afsi_matrix_set_column_block(h, int(nbytes)))
+
+
+def afsi_matrix_get_column_block(h) -> int:
+    v = C.c_int64(0)
+    _check(lib().afsi_matrix_get_column_block(h, C.byref(v)))
+    return v.value
 
 
 def afsi_filter_coefficients(lmin, lmax, a, b, kmax, damping="jackson", m_exp=0.5) -> np.ndarray:

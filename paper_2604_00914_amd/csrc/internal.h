@@ -86,6 +86,9 @@ struct MatView {
     // at least one entry per two rows lies within one column of the diagonal: the
     // Clenshaw step stages each workgroup's rows of the source block in LDS
     bool stage_near = false;
+    // column-block width (bytes) of a product's passes over the dense block: 0 = whole
+    // rows in one pass (see afsi_matrix_set_column_block)
+    int64_t seg_bytes = 0;
 };
 
 }  // namespace afsi
@@ -99,6 +102,7 @@ struct afsi_matrix_s {
     void *d_val64 = nullptr;
     void *d_val32 = nullptr;
     int64_t near_nnz = 0;  // entries with |column - row| <= 1
+    int64_t seg_bytes = 0; // column-block width of the products (0 = whole rows)
     double lmin = 0, lmax = 0;
     bool has_bounds = false;
     std::mutex mu;
@@ -152,7 +156,8 @@ struct BatchArgs {
 // matrix with near-diagonal entries tries X(1, 64) first.)
 #define AFSI_GROUPED_MAPPINGS(X)                                                                    \
     X(2, 64) X(4, 32) X(4, 64) X(3, 64) X(5, 64) X(3, 32) X(5, 32) X(2, 32) X(6, 64) X(8, 64)      \
-    X(1, 64) X(1, 32) X(3, 16) X(1, 16) X(3, 8)
+    X(1, 64) X(1, 32) X(3, 16) X(1, 16) X(3, 8) X(1, 8) X(1, 4)
+
 
 // Smallest row width, in 16-byte vectors, of at least p16 that the grouped kernel
 // maps exactly, or -1 if p16 is wider than every mapping.

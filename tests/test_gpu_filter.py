@@ -597,3 +597,43 @@ def test_grouped_rejects_overlapping_slices():
     with pytest.raises(afsi.AfsiError):  # two slices share a block
         afsi.afsi_clenshaw_step_grouped(M.handle, [(g, X, Q0, Q1), (g, X, t.zeros_like(X), t.zeros_like(X))])
     M.close()
+
+
+@pytest.mark.parametrize("cplx,single", [(False, False), (False, True), (True, False)])
+def test_column_blocks_give_the_same_bits(cplx, single):
+    # products in column blocks of the dense operand (afsi_matrix_set_column_block, the
+    # MaSpMM loop over column blocks) against whole-row passes: identical bits for every
+    # block width, and the oracle's filter on sampled columns
+    from workloads import random_banded_symmetric
+
+    t = torch()
+    A = random_banded_symmetric(6000, seed=5)
+    if cplx:
+        A = _ragged_symmetric(complex_=True)
+    lmin, lmax = gershgorin_bounds(A)
+    mid = 0.5 * (lmin + lmax)
+    a, b = mid - 0.05 * (lmax - lmin), mid + 0.05 * (lmax - lmin)
+    p, k = 160, 9
+    X0 = start_block(A.n, p, seed=3, complex_=cplx)
+    c = afsi.afsi_filter_coefficients(lmin, lmax, a, b, k, "jackson")
+    M = afsi.Matrix(A, bounds=(lmin, lmax))
+    assert afsi.afsi_matrix_get_column_block(M.handle) == 0
+    dt = _tdt(cplx, single)
+    X = t.from_numpy(X0).to(DEV).to(dt)
+    outs = {}
+    for seg in (0, 64, 128, 256):
+        afsi.afsi_matrix_set_column_block(M.handle, seg)
+        Y, W = t.zeros_like(X), t.zeros_like(X)
+        afsi.afsi_filter_block(M.handle, c, k, X, Y, W)
+        t.cuda.synchronize()
+        outs[seg] = Y.cpu().numpy()
+    for seg in (64, 128, 256):
+        assert np.array_equal(outs[seg], outs[0]), seg
+    for bad in (24, 48, -16):
+        with pytest.raises(afsi.AfsiError):
+            afsi.afsi_matrix_set_column_block(M.handle, bad)
+    M.close()
+    cols = [0, 77, p - 1]
+    ref = oracle_filter(A, np.ascontiguousarray(X0[:, cols]), lmin, lmax, a, b, k)
+    _check(outs[64][:, cols].astype(np.complex128 if cplx else np.float64), ref,
+           f32_tol(k) if single else F64_TOL)

@@ -155,3 +155,99 @@ def test_lanczos_bounds_enclose_spectrum(cplx):
     assert lo <= w[0] and hi >= w[-1] and hi - lo < 1.2 * (w[-1] - w[0])
     assert afsi.afsi_get_spectral_bounds(M.handle) == (lo, hi)
     M.close()
+
+
+def test_spurious_ritz_scenario_matches_oracle():
+    # Section 3.3.2 on the chain_400 workload: a Ritz value at the window's centre with a
+    # residual near 0.11 stays for the whole solve; Algorithm 4's tau_s test and n_check
+    # rule still stop with the exact count.  Same start block as the oracle.
+    A, (lo, hi), (a, b), cfg = build_config("chain_400")
+    exact = closed_form.lap2d_eigs(400, 1)
+    exact = exact[(exact >= a) & (exact <= b)]
+    X0 = start_block(A.n, cfg.p, seed=0)
+    st, lam, res, r, V = gpu_solve(A, a, b, lo, hi, X0, cfg.degree, max_iter=120)
+    o = osolver.solve(A, a, b, lo, hi, X0, osolver.Options(kmax=cfg.degree, max_iter=120))
+    assert st == 0 and r.converged and r.count == exact.size == o.eigenvalues.size == 10
+    _check_pairs(A, lam, V, exact, hi, 1e-10, 1e-9)
+    assert np.max(np.abs(lam - o.eigenvalues)) <= 1e-10 * hi
+    assert abs(r.iterations - o.iterations) <= 2
+
+
+def test_spurious_ritz_value_seen_by_the_gpu_steps():
+    # the same scenario through the boundary's step calls (filter, Cholesky QR,
+    # Rayleigh-Ritz, residuals, spurious-value test): after 15 iterations the GPU's Ritz
+    # values in [a, b] equal the oracle's, one of them with residual >= 0.1 > tau_s, and
+    # the test sets it aside once n_check repeats
+    from oracle import coefficients as co
+    from oracle import dense as odense
+    from oracle.filter import clenshaw_filter
+
+    t = torch()
+    A, (lo, hi), (a, b), cfg = build_config("chain_400")
+    M = afsi.Matrix(A, bounds=(lo, hi))
+    X0 = start_block(A.n, cfg.p, seed=0)
+    c = afsi.afsi_filter_coefficients(lo, hi, a, b, cfg.degree, "jackson")
+    X = to_dev(X0)
+    Y, W = t.empty_like(X), t.empty_like(X)
+    afsi.afsi_orthonormalize(None, X, W)
+    n_check = 0
+    for it in range(15):
+        afsi.afsi_filter_block(M.handle, c, cfg.degree, X, Y, W)
+        afsi.afsi_orthonormalize(None, Y, W)
+        ritz = afsi.afsi_rayleigh_ritz(M.handle, Y, X, W)   # V -> X, AV -> W
+        res = afsi.afsi_residual_norms(X, W, ritz)
+        inside = (ritz >= a) & (ritz <= b)
+        I, lock, done, n_check = afsi.afsi_lock_select(ritz, res, inside, a, b, 0.0, 0, n_check)
+    M.close()
+    tau_s = np.min(np.minimum(np.abs(ritz[inside] - a), np.abs(ritz[inside] - b)))
+    spurious = inside & (res >= tau_s)
+    assert spurious.sum() == 1 and res[spurious][0] >= 0.1
+    assert not I[spurious].any() and I.sum() == inside.sum() - 1
+    # the oracle's steps from the same start block
+    l1, l2 = co.affine_map(lo, hi)
+    co_ = co.filter_coefficients(lo, hi, a, b, cfg.degree, "jackson")
+    Q = odense.orthonormalize(X0)
+    for it in range(15):
+        Q = odense.orthonormalize(clenshaw_filter(A, Q, co_, l1, l2))
+        w, Q, AQ = odense.rayleigh_ritz(A, Q)
+    assert np.max(np.abs(np.sort(ritz[inside]) - np.sort(w[(w >= a) & (w <= b)]))) <= 1e-9 * hi
+
+
+@pytest.mark.parametrize("mode,value", [("m", 0.0), ("m", 1.0), ("m", 3.0), ("fixed_k1", 60)])
+def test_sensitivity_modes_match_oracle(mode, value):
+    # the modes of Section 4.2's parameter study on lap2d_64 (40 eigenvalues, closed form):
+    # the adaptive filter with Lanczos damping exponent m (k^(1) from eq. (compute_k_1),
+    # maximum ceil(2.5 k^(1))), and the fixed degree k^(1) = ceil(C_r) - 1 of the C_r
+    # sweep; count, eigenvalues, iterations and average degree against the oracle on the
+    # same start block
+    import math
+
+    from oracle import coefficients as co
+
+    A, (lo, hi), (a, b), cfg = build_config("lap2d_64")
+    exact = closed_form.lap2d_eigs(64)
+    exact = exact[(exact >= a) & (exact <= b)]
+    X0 = start_block(A.n, cfg.p, seed=2)
+    if mode == "m":
+        alpha, beta = co.interval_angles(a, b, lo, hi)
+        k1 = co.initial_degree(alpha, beta, 1.4)
+        kmax, m_exp, adaptive = math.ceil(2.5 * k1), value, True
+    else:
+        k1 = kmax = math.ceil(value) - 1
+        m_exp, adaptive = 0.5, False
+    t = torch()
+    M = afsi.Matrix(A, bounds=(lo, hi))
+    o = afsi.afsi_options_default(kmax)
+    o.k_init, o.adaptive, o.damping, o.m_exp, o.max_iter = k1, int(adaptive), afsi.DAMP_LANCZOS, m_exp, 400
+    E = t.zeros((A.n, cfg.p), dtype=t.float64, device=DEV)
+    st, lam, res, r = afsi.afsi_solve(M.handle, a, b, o, to_dev(X0), E, cfg.p)
+    V = E[:, : r.count].cpu().numpy()
+    M.close()
+    ref = osolver.solve(A, a, b, lo, hi, X0, osolver.Options(
+        kmax=kmax, damping="lanczos", m_exp=m_exp, adaptive=adaptive, k_init=k1, max_iter=400))
+    assert st == 0 and r.converged and ref.converged
+    assert r.count == ref.eigenvalues.size == exact.size
+    _check_pairs(A, lam, V, exact, hi, 1e-10, 1e-9)
+    assert np.max(np.abs(lam - ref.eigenvalues)) <= 1e-10 * hi
+    assert abs(r.iterations - ref.iterations) <= 2
+    assert abs(r.avg_degree - ref.avg_degree) <= 2.0

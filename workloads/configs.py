@@ -131,6 +131,28 @@ CONFIGS = {
 }
 
 
+# The spurious-Ritz-value scenario (Section 3.3.2) on a synthetic matrix: the 1D
+# Dirichlet chain of N = 400 points with diagonal 4 (the 2D recipe on an N x 1 grid;
+# eigenvalues 4 - 2cos(j pi / 401), symmetric about 4) and exact bounds symmetric about
+# 4, so the filter of a window centred at 4 takes equal values at 4 - x and 4 + x.  The
+# window holds the 10 eigenvalues nearest 4 (ends mid-gap); with p = 15 the block holds
+# them, two outside pairs and one vector of the third pair, which no filter of this
+# window can separate: its Ritz value sits at 4, inside, with a residual near 0.11.
+CONFIGS["chain_400"] = WorkloadConfig(
+    name="chain_400",
+    description="1D Dirichlet chain N=400, diagonal 4, window of 10 eigenvalues centred at 4",
+    make_matrix=lambda size, seed: laplacian_2d_dirichlet(size, 1),
+    size=400,
+    p=15,
+    degree=120,
+    damping="jackson",
+    complex_=False,
+    filter_dtypes=("f64",),
+    interval=lambda lo, hi: (3.921676678665852, 4.078323321334147),
+    exact_bounds=lambda N: (4.0 - 2.0 * np.cos(np.pi / (N + 1)), 4.0 + 2.0 * np.cos(np.pi / (N + 1))),
+)
+
+
 def build_config(name: str, size: int | None = None, seed: int = 0):
     """Return (A, (lo, hi), (a, b), cfg) for a named workload, optionally resized."""
     cfg = CONFIGS[name]
