@@ -637,3 +637,39 @@ def test_column_blocks_give_the_same_bits(cplx, single):
     ref = oracle_filter(A, np.ascontiguousarray(X0[:, cols]), lmin, lmax, a, b, k)
     _check(outs[64][:, cols].astype(np.complex128 if cplx else np.float64), ref,
            f32_tol(k) if single else F64_TOL)
+
+
+@pytest.mark.parametrize("name", ["lap3d_pot_100", "tb3d_64"])
+@pytest.mark.parametrize("p,pad", [(1, 0), (2, 0), (3, 0), (1, 40), (3, 5), (8, 0), (16, 0)])
+def test_narrow_products_full_size(name, p, pad):
+    # the one-lane-per-row kernel at full size (the bounds estimate's single vectors,
+    # narrow Krylov blocks): A X on p <= 16 columns, inside a wider block (ld = p + pad)
+    # and contiguous, against the oracle's CSR product; the bits equal a column-by-column
+    # run (every column takes the same entry order)
+    from oracle import native
+
+    t = torch()
+    A, (lo, hi), _, cfg = build_config(name)
+    cplx = A.is_complex
+    X0 = start_block(A.n, p, seed=p + pad, complex_=cplx)
+    M = afsi.Matrix(A, bounds=(lo, hi))
+    dt = t.complex128 if cplx else t.float64
+    Xs = t.zeros((A.n, p + pad), dtype=dt, device=DEV)
+    Ys = t.zeros_like(Xs)
+    Xs[:, :p] = t.from_numpy(X0).to(DEV)
+    X, Y = Xs[:, :p], Ys[:, :p]
+    afsi.afsi_spmm(M.handle, X, Y)
+    t.cuda.synchronize()
+    got = Y.cpu().numpy()
+    ref = native.spmm(A, X0)
+    assert rel_fro(got, ref) <= 1e-14 and max_rel(got, ref) <= 1e-13
+    if pad:
+        assert not Ys[:, p:].cpu().numpy().any()  # the rest of the wide block untouched
+    one = t.zeros((A.n, 1), dtype=dt, device=DEV)
+    out = t.zeros_like(one)
+    for j in range(p):
+        one.copy_(X[:, j:j + 1])
+        afsi.afsi_spmm(M.handle, one, out)
+        t.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy()[:, 0], got[:, j]), j
+    M.close()
