@@ -15,7 +15,10 @@
 
 namespace afsi {
 
-template <class Tr, int VN, int L, int U, bool STAGE>
+// STEADY: every slice of the launch subtracts its b_{j+2} and adds alpha X (the steady
+// products of a filter), known at compile time as in the single-block kernel; otherwise
+// each slice's flags are read at run time.
+template <class Tr, int VN, int L, int U, bool STAGE, bool STEADY>
 __global__ __launch_bounds__(256) void clenshaw_grouped_kernel(
     int n, const int *__restrict__ rp, const int *__restrict__ ci,
     const typename Tr::val *__restrict__ va, int group, int nblocks, const GroupArgs args) {
@@ -50,9 +53,9 @@ __global__ __launch_bounds__(256) void clenshaw_grouped_kernel(
     const vec *src = s == 0 ? X : (s == 1 ? P0 : P1);
     vec *dst = args.dst[g] == 1 ? P0 : P1;
     const int64_t ldv = args.ldv[g];
-    const bool hv = args.has_v[g] != 0;
+    const bool hv = STEADY || args.has_v[g] != 0;
     const scal alpha = (scal)args.alpha[g];
-    const bool hx = args.alpha[g] != 0.0;
+    const bool hx = STEADY || args.alpha[g] != 0.0;
     constexpr bool EARLY = L < 64 && VN <= 3;  // as in clenshaw_step_kernel
     const int64_t base = (int64_t)row * ldv + sub;
     vec vin[VN], xin[VN];
@@ -88,15 +91,22 @@ void launch_grouped(const MatView &A, GroupArgs &args, hipStream_t s) {
     const Grid g = xcd_grid(rows, rows_per_block);
     if constexpr (VN <= 3 && L == 64) {
         if (A.stage_near) {
-            hipLaunchKernelGGL((clenshaw_grouped_kernel<Tr, VN, L, U, true>), dim3((unsigned)g.grid),
-                               dim3(256), 0, s, (int)A.n, A.rp, A.ci,
+            hipLaunchKernelGGL((clenshaw_grouped_kernel<Tr, VN, L, U, true, false>),
+                               dim3((unsigned)g.grid), dim3(256), 0, s, (int)A.n, A.rp, A.ci,
                                (const typename Tr::val *)A.val, g.group, g.nblocks, args);
             return;
         }
     }
-    hipLaunchKernelGGL((clenshaw_grouped_kernel<Tr, VN, L, U, false>), dim3((unsigned)g.grid),
-                       dim3(256), 0, s, (int)A.n, A.rp, A.ci, (const typename Tr::val *)A.val,
-                       g.group, g.nblocks, args);
+    bool steady = true;
+    for (int k = 0; k < args.ngroups; ++k) steady = steady && args.has_v[k] && args.alpha[k] != 0.0;
+    if (steady)
+        hipLaunchKernelGGL((clenshaw_grouped_kernel<Tr, VN, L, U, false, true>), dim3((unsigned)g.grid),
+                           dim3(256), 0, s, (int)A.n, A.rp, A.ci, (const typename Tr::val *)A.val,
+                           g.group, g.nblocks, args);
+    else
+        hipLaunchKernelGGL((clenshaw_grouped_kernel<Tr, VN, L, U, false, false>), dim3((unsigned)g.grid),
+                           dim3(256), 0, s, (int)A.n, A.rp, A.ci, (const typename Tr::val *)A.val,
+                           g.group, g.nblocks, args);
 }
 
 // true if p16 has an exact lane mapping (the single-block kernel's table, same order)
