@@ -556,10 +556,13 @@ void dense_thread(Pool *P, int worker) {
                 s.ev_recorded = true;
             }
         } catch (const Error &e) {
+            // nothing of this request may still run when its columns are given back
+            if (s.ev_recorded) (void)hipEventSynchronize(s.ev);
             (void)hipStreamSynchronize(st);
             finish(P, s, e.status, afsi_last_error());
             s.phase = PH_GONE;
         } catch (const std::exception &e) {
+            if (s.ev_recorded) (void)hipEventSynchronize(s.ev);
             (void)hipStreamSynchronize(st);
             finish(P, s, AFSI_E_NOMEM, e.what());
             s.phase = PH_GONE;
