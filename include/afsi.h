@@ -456,9 +456,16 @@ typedef struct {
     int32_t basis;       /* m: basis columns before a restart, 2 s <= m <= n */
     double tau_c;        /* lock when ||A u - lambda u|| < tau_c ||A|| */
     int32_t max_cycles;  /* restart-cycle limit */
+    int32_t mixed;       /* 1: the filter runs in FP32 (complex FP32 for a complex A) on
+                            converted copies of the Krylov blocks, everything else in FP64
+                            (use tau_c >= 1e-6).  Rayleigh-Ritz on B can only separate
+                            eigenvectors whose filter values differ by more than the FP32
+                            operator's error (~1e-7): fine for windows the filter resolves,
+                            but pairs deep inside a flat filter plateau then never lock.
+                            0: FP64 throughout */
 } afsi_lanczos_options;
 
-/* Jackson damping, block 4, basis 128, tau_c 1e-10, 200 cycles, at degree `degree`. */
+/* Jackson damping, block 4, basis 128, tau_c 1e-10, 200 cycles, FP64, at degree `degree`. */
 void afsi_lanczos_options_default(afsi_lanczos_options *o, int degree);
 
 typedef struct {

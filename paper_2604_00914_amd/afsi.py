@@ -65,7 +65,7 @@ class afsi_result(C.Structure):
 class afsi_lanczos_options(C.Structure):
     _fields_ = [("degree", C.c_int32), ("damping", C.c_int32), ("m_exp", C.c_double),
                 ("block", C.c_int32), ("basis", C.c_int32), ("tau_c", C.c_double),
-                ("max_cycles", C.c_int32)]
+                ("max_cycles", C.c_int32), ("mixed", C.c_int32)]
 
 
 class afsi_lanczos_result(C.Structure):

@@ -18,6 +18,8 @@
 //   * stop when no wanted pair is left and the largest remaining theta plus its
 //     B-residual stays below eta; else restart thick with the unlocked Ritz vectors
 //     of largest theta plus the Krylov continuation block.
+// The mixed form applies the filter to FP32 copies of the Krylov blocks (complex FP32
+// for a complex A); everything else stays FP64.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -88,6 +90,7 @@ void afsi_lanczos_options_default(afsi_lanczos_options *o, int degree) {
     o->basis = 128;
     o->tau_c = 1e-10;
     o->max_cycles = 200;
+    o->mixed = 0;
 }
 
 int afsi_filtered_lanczos(afsi_matrix_t A, double a, double b, const afsi_lanczos_options *opts,
@@ -133,6 +136,11 @@ int afsi_filtered_lanczos(afsi_matrix_t A, double a, double b, const afsi_lanczo
         Dev V(blk), W(blk), U(blk), BU(blk), AU(blk);
         Dev Lout((size_t)n * m * eb);  // locked pairs outside [a, b] (deflated, not returned)
         Dev Zb((size_t)n * s * eb), BZ((size_t)n * s * eb), Zw((size_t)n * s * eb);
+        // mixed form: the filter runs on FP32 copies (complex FP32 for a complex A)
+        const bool mixed = opts->mixed != 0;
+        const int fdt = mixed ? (cplx ? AFSI_C64 : AFSI_R32) : dt;
+        const size_t fbytes = mixed ? (size_t)n * s * elem_bytes(fdt) : 0;
+        Dev F0(fbytes), F1(fbytes), F2(fbytes);
         Dev Hd(sizeof(double) * comp * cap * cap), Yd(sizeof(double) * comp * cap * cap);
         Dev dots(sizeof(double) * cap);
         std::vector<double> H((size_t)comp * cap * cap), Y((size_t)comp * cap * cap),
@@ -142,7 +150,15 @@ int afsi_filtered_lanczos(afsi_matrix_t A, double a, double b, const afsi_lanczo
         int64_t n_out = 0, filtered = 0;
 
         auto filt = [&](void *out) {  // out (n x s, ld s) = B Zb
-            filter_apply(A, coeffs.data(), k, dt, Zb.p, out, Zw.p, s, s, st);
+            if (!mixed) {
+                filter_apply(A, coeffs.data(), k, dt, Zb.p, out, Zw.p, s, s, st);
+            } else {
+                afsi_block z{Zb.p, n, s, s, dt}, z32{F0.p, n, s, s, fdt};
+                launch_convert(z, z32, st);
+                filter_apply(A, coeffs.data(), k, fdt, F0.p, F1.p, F2.p, s, s, st);
+                afsi_block y32{F1.p, n, s, s, fdt}, y{out, n, s, s, dt};
+                launch_convert(y32, y, st);
+            }
             filtered += s;
         };
         // Zb <- Zb made orthogonal (twice) to V[:, :cols] and the locked vectors, orthonormal

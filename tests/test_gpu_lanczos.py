@@ -25,11 +25,13 @@ from workloads import (
 pytestmark = pytest.mark.gpu
 
 
-def _gpu(A, a, b, bounds, X0, degree, block, basis, max_cycles=200, capacity=None):
+def _gpu(A, a, b, bounds, X0, degree, block, basis, max_cycles=200, capacity=None, mixed=False):
     t = torch()
     M = afsi.Matrix(A, bounds=bounds)
     o = afsi.afsi_lanczos_options_default(degree)
     o.block, o.basis, o.max_cycles = block, basis, max_cycles
+    if mixed:
+        o.mixed, o.tau_c = 1, 1e-6
     cap = capacity or 2 * basis
     E = t.zeros((A.n, cap), dtype=t.complex128 if A.is_complex else t.float64, device=DEV)
     st, lam, res, r = afsi.afsi_filtered_lanczos(M.handle, a, b, o, to_dev(X0), E)
@@ -117,3 +119,30 @@ def test_errors_and_cycle_limit():
     st, lam, res, r = afsi.afsi_filtered_lanczos(M.handle, 6.9, 7.1, o, X0, E)
     assert r.cycles == 1 and (st == -6) == (not r.converged)  # stops at the limit
     M.close()
+
+
+@pytest.mark.parametrize("case", ["config1", "tb"])
+def test_mixed_form_within_tolerance(case):
+    # the FP32 (complex FP32) filter with FP64 Krylov basis, Rayleigh-Ritz and residuals,
+    # locking at 1e-6 ||A||: exact counts, eigenvalues within 1e-5 ||A|| of the exact ones
+    # and of the FP64 oracle's, residuals <= 1e-5 ||A||
+    if case == "config1":
+        A, (lmin, lmax), (a, b), cfg = build_config("lap2d_64")
+        ref = closed_form.lap2d_eigs(64)
+        ref = ref[(ref >= a) & (ref <= b)]
+        deg, block, basis = cfg.degree, 8, 128
+    else:
+        A = tight_binding_3d_periodic(12, seed=1)
+        w, a, b, ref = _window(A, 12)
+        lmin, lmax = w[0] - 1e-2, w[-1] + 1e-2
+        deg, block, basis = 200, 4, 64
+    normA = max(abs(lmin), abs(lmax))
+    X0 = start_block(A.n, block, seed=5, complex_=A.is_complex)
+    orc = ol.filtered_lanczos(A, a, b, lmin, lmax, X0, ol.LanczosOptions(degree=deg, block=block, basis=basis))
+    st, lam, res, V, r = _gpu(A, a, b, (lmin, lmax), X0, deg, block, basis, mixed=True)
+    assert st == 0 and r.converged and lam.size == ref.size == orc.eigenvalues.size
+    assert np.max(np.abs(lam - np.sort(ref))) <= 1e-5 * normA
+    assert np.max(np.abs(lam - orc.eigenvalues)) <= 1e-5 * normA
+    R = A.to_scipy() @ V - V * lam[None, :]
+    assert np.max(np.linalg.norm(R, axis=0)) <= 1e-5 * normA
+    assert np.max(np.abs(V.conj().T @ V - np.eye(lam.size))) < 1e-8
