@@ -97,6 +97,7 @@ MatView matrix_view(afsi_matrix_t A, int block_dtype, hipStream_t stream) {
     MatView v{A->n, A->d_rp, A->d_ci, A->d_val64};
     v.stage_near = 2 * A->near_nnz >= A->n;
     v.seg_bytes = A->seg_bytes;
+    v.band = A->band;
     if (!is_fp64(block_dtype)) {
         std::lock_guard<std::mutex> lk(A->mu);
         if (!A->d_val32) {
@@ -459,6 +460,7 @@ int afsi_matrix_create_csr(int device, int64_t n, int64_t nnz, const int64_t *ro
         AFSI_REQUIRE(nnz == 0 || (col_idx && vals), "col_idx / vals are NULL");
         AFSI_REQUIRE(row_ptr[0] == 0 && row_ptr[n] == nnz, "row_ptr must start at 0 and end at nnz");
         std::vector<int> rp32(n + 1);
+        std::vector<int64_t> reach(n);
         int64_t near_nnz = 0;
         for (int64_t i = 0; i < n; ++i) {
             AFSI_REQUIRE(row_ptr[i + 1] >= row_ptr[i], "row_ptr decreases at row %lld", (long long)i);
@@ -469,6 +471,9 @@ int afsi_matrix_create_csr(int device, int64_t n, int64_t nnz, const int64_t *ro
                              "columns not strictly increasing in row %lld", (long long)i);
                 near_nnz += col_idx[e] >= i - 1 && col_idx[e] <= i + 1;
             }
+            reach[i] = row_ptr[i + 1] > row_ptr[i]
+                           ? std::max<int64_t>(i - col_idx[row_ptr[i]], col_idx[row_ptr[i + 1] - 1] - i)
+                           : 0;
             rp32[i] = (int)row_ptr[i];
         }
         rp32[n] = (int)nnz;
@@ -478,6 +483,10 @@ int afsi_matrix_create_csr(int device, int64_t n, int64_t nnz, const int64_t *ro
         A->n = n;
         A->nnz = nnz;
         A->near_nnz = near_nnz;
+        if (n > 0) {
+            std::nth_element(reach.begin(), reach.begin() + n / 2, reach.end());
+            A->band = std::max<int64_t>(0, reach[n / 2]);
+        }
         A->dtype = val_dtype;
         const size_t vbytes = (size_t)nnz * elem_bytes(val_dtype);
         try {

@@ -88,7 +88,7 @@ void launch_grouped(const MatView &A, GroupArgs &args, hipStream_t s) {
     args.npad = (A.n + rows_per_block - 1) / rows_per_block * rows_per_block;
     const int64_t rows = args.npad * args.ngroups;
     AFSI_REQUIRE(rows / rows_per_block < (1LL << 31), "grouped step: too many rows");
-    const Grid g = xcd_grid(rows, rows_per_block);
+    const Grid g = xcd_grid(rows, rows_per_block, run_rows_for(A, VN * L * 16, rows_per_block));
     if constexpr (VN <= 3 && L == 64) {
         if (A.stage_near) {
             hipLaunchKernelGGL((clenshaw_grouped_kernel<Tr, VN, L, U, true, false>),

@@ -89,6 +89,8 @@ struct MatView {
     // column-block width (bytes) of a product's passes over the dense block: 0 = whole
     // rows in one pass (see afsi_matrix_set_column_block)
     int64_t seg_bytes = 0;
+    // median over rows of the largest |column - row| (the reach of a banded matrix)
+    int64_t band = 0;
 };
 
 }  // namespace afsi
@@ -103,6 +105,7 @@ struct afsi_matrix_s {
     void *d_val32 = nullptr;
     int64_t near_nnz = 0;  // entries with |column - row| <= 1
     int64_t seg_bytes = 0; // column-block width of the products (0 = whole rows)
+    int64_t band = 0;      // median over rows of the largest |column - row|
     double lmin = 0, lmax = 0;
     bool has_bounds = false;
     std::mutex mu;
