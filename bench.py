@@ -336,6 +336,10 @@ def main():
     if not args.no_serve:
         out["serve"] = serve_rates(afsi, M, args.serve_requests)
 
+    out["paper_context"] = paper_context()
+    # the same rate for this GPU's steady product (nonzeros x block columns per second)
+    out["paper_context"]["this_gpu_steady_product_nnz_per_s"] = float(
+        f"{A.nnz * p / (steady_launch_ms * 1e-3):.3g}")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, p, k, lmin, lmax, a, b, cfg, sx, args.cpu_sample_steps)
     M.close()
@@ -962,6 +966,32 @@ def serve_rates(afsi, M_slices, num, loads=(0.5, 0.8, 0.95)):
         M.close()
     M1.close()
     M2.close()
+    return out
+
+
+# Table 1 of the paper (Section 4.1): rows, nonzeros and eigenvalue count of each test matrix
+PAPER_TABLE1 = {"Ge87H76": (112985, 7892195, 212), "Ge99H100": (112985, 8451395, 250),
+                "Si41Ge41H72": (185639, 15011265, 218), "Si87H76": (240369, 10661631, 213),
+                "Ga41As41H72": (268096, 18488476, 201)}
+
+
+def paper_context():
+    """The paper's own AdaPolySI figures as context (Tables 1 and 2, Section 4.1: one CPU
+    socket, 28 OpenMP threads, FP64, SuiteSparse DFT Hamiltonians of 1.1e5-2.7e5 rows,
+    residual 1e-10 ||A||): eigenpairs/s (#evals / runtime) and the rate of sparse
+    matrix-vector products (SpMVs x nnz / runtime, nonzeros x vectors per second, a
+    lower bound on its SpMM rate since the whole solve is timed).  Different hardware
+    and matrices: not a target."""
+    rows = [l.strip().split(",") for l in open(os.path.join(ROOT, "tests", "golden", "paper_table2.csv"))
+            if l.strip() and not l.startswith("#") and not l.startswith("matrix")]
+    out = {"hardware": "one CPU socket, 28 OpenMP threads, FP64 (Section 4)", "per_matrix": {}}
+    for m, method, avgdeg, it, spmvs, rt, res in rows:
+        if method != "AdaPolySI":
+            continue
+        n, nnz, ev = PAPER_TABLE1[m]
+        out["per_matrix"][m] = {"n": n, "eigenpairs": ev, "runtime_s": float(rt),
+                                "eigenpairs_per_s": round(ev / float(rt), 2),
+                                "spmv_nnz_per_s": float(f"{int(spmvs) * nnz / float(rt):.3g}")}
     return out
 
 
