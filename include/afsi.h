@@ -482,8 +482,8 @@ typedef struct {
  * (device, R64 for a real A, C128 for a complex A; read only).  On return:
  * eigenvalues[count] and residuals[count] (host, ascending), eigenvectors in columns
  * 0..count-1 of `evecs` (device, n x capacity, X0's dtype).  The library allocates its
- * working blocks (five n x (basis + block) blocks and one n x basis block) for the
- * call.  Returns AFSI_E_NOCONV with the pairs found if max_cycles is reached,
+ * working blocks for the call: five n x (basis + block) blocks, one n x basis block and
+ * three n x block blocks (three more in FP32 for the mixed form).  Returns AFSI_E_NOCONV with the pairs found if max_cycles is reached,
  * AFSI_E_INVALID on bad arguments or if more than `capacity` pairs lock.
  * Synchronises `stream`.
  */
