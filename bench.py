@@ -94,6 +94,9 @@ def main():
     ap.add_argument("--sensitivity", default=None, metavar="OUT",
                     help="only run the parameter-sensitivity solves (damping exponent m, "
                          "tau_a, C_r adaptive vs fixed); one JSON line per solve into OUT")
+    ap.add_argument("--bandwidth", default=None, metavar="OUT",
+                    help="only measure a device copy and a 3-read/1-write pass against the "
+                         "working-set size (memory-side cache vs HBM); one JSON line per size")
     ap.add_argument("--irregular", default=None, metavar="OUT",
                     help="only measure the steady product of the irregular n = 2e6 matrix at "
                          "p = 640 FP32; one JSON line into OUT")
@@ -127,6 +130,9 @@ def main():
         return
     if args.sensitivity:
         sensitivity(afsi, torch, dev, args.sensitivity)
+        return
+    if args.bandwidth:
+        bandwidth_sweep(torch, dev, args.bandwidth)
         return
     if args.irregular:
         rec = irregular_record(afsi, torch, dev)
@@ -814,6 +820,34 @@ def lanczos_rates(afsi, torch, dev, seeds=(0, 1, 2, 3, 4)):
     if f and m_ and f["eigenpairs_per_s"] > 0:
         out["mixed_vs_fp64_equal_accuracy"] = round(m_["eigenpairs_per_s"] / f["eigenpairs_per_s"], 3)
     return out
+
+
+def bandwidth_sweep(torch, dev, path):
+    """Plain streaming references against working-set size: torch's device copy (read one
+    FP64 buffer, write one) and addcmul_ (read three, write one in place), repeated back
+    to back and timed with HIP events; sets up to ~256 MB stay in the memory-side cache."""
+    with open(path, "w") as fh:
+        for mb in (16, 32, 64, 96, 128, 256, 512, 2048, 4096):
+            n = mb * (1 << 20) // 8
+            a = torch.randn(n, dtype=torch.float64, device=dev)
+            b, c, d = torch.empty_like(a), torch.randn_like(a), torch.randn_like(a)
+            reps = max(5, 20000 // mb)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            rec = {"MB_per_buffer": mb, "copy_ws_MB": 2 * mb, "3r1w_ws_MB": 3 * mb}
+            for name, fn, passes in (("copy_GBs", lambda: b.copy_(a), 2),
+                                     ("3r1w_GBs", lambda: b.addcmul_(c, d), 4)):
+                for _ in range(3):
+                    fn()
+                e0.record()
+                for _ in range(reps):
+                    fn()
+                e1.record()
+                torch.cuda.synchronize()
+                rec[name] = round(passes * n * 8 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+            log(f"bandwidth: {rec}")
+            fh.write(json.dumps(rec) + "\n")
+            del a, b, c, d
+            torch.cuda.empty_cache()
 
 
 def irregular_record(afsi, torch, dev, products=8):
