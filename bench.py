@@ -768,7 +768,8 @@ def eigencount_rates(afsi, torch, dev, probes=64):
 # operator resolves, and the mixed Lanczos does not lock those pairs)
 LANCZOS_RUNS = [("lap2d_64", 8, 128, 60, "fp64", 1e-10), ("lap2d_64", 8, 128, 60, "fp64", 1e-6),
                 ("lap2d_64", 8, 128, 60, "mixed", 1e-6), ("lap3d_pot_27", 32, 512, 120, "fp64", 1e-10),
-                ("lap3d_pot_27", 32, 512, 200, "fp64", 1e-10), ("lap3d_pot_27", 32, 512, 200, "fp64", 1e-6)]
+                ("lap3d_pot_27", 32, 512, 200, "fp64", 1e-10), ("lap3d_pot_27", 32, 512, 300, "fp64", 1e-10),
+                ("lap3d_pot_27", 32, 512, 200, "fp64", 1e-6)]
 
 
 def lanczos_rates(afsi, torch, dev, seeds=(0, 1, 2, 3, 4)):
