@@ -8,10 +8,11 @@
 //  * host_eigh: Hermitian eigendecomposition B = U diag(w) U^H (Golub & Van Loan,
 //    Matrix Computations, ch. 8.3): Householder reduction to tridiagonal form
 //    (complex reflectors for Hermitian B), a diagonal unitary scaling that makes the
-//    off-diagonal real, the implicit symmetric QR iteration with Wilkinson shifts on
-//    the real tridiagonal (its plane rotations recorded), then
-//    U = H_0 ... H_{p-3} diag(delta) Z.  Rotations and reflectors are applied to
-//    column chunks of the eigenvector matrix in parallel.
+//    off-diagonal real, the tridiagonal's eigenpairs by divide and conquer (Golub & Van
+//    Loan ch. 8.4; Gu & Eisenstat's eigenvectors) with the implicit symmetric QR
+//    iteration with Wilkinson shifts for blocks of at most 32 (and as the fallback), then
+//    U = H_0 ... H_{p-3} diag(delta) Z.  Reflectors (and the QR path's rotations) are
+//    applied to column chunks of the eigenvector matrix in parallel.
 //
 // Compiled twice (AFSI_ISA_NS = generic, and avx2 with -mavx2 -mfma); the entry
 // points in host_linalg_dispatch.cpp pick one at run time.
@@ -311,6 +312,246 @@ static void rotate_columns(LineMatrix<double> &Zt, const std::vector<Rot> &rots,
     }
 }
 
+// ---------------------------------------------------------------- divide and conquer
+//
+// Eigenpairs of a real symmetric tridiagonal matrix (d, e) by Cuppen's divide and
+// conquer with Gu and Eisenstat's eigenvector formula (SIAM J. Matrix Anal. Appl. 16,
+// 1995), as in Golub & Van Loan ch. 8.4.  The matrix is torn at its middle,
+//   T = diag(T1', T2') + rho v v^T,  rho = |beta|, v = e_{m-1} + sign(beta) e_m,
+// where beta = e[m-1] and T1', T2' have |beta| taken off their touching diagonal
+// entries; the halves are solved recursively (T_i' = Q_i D_i Q_i^T) and the rank-one
+// update D + rho z z^T, z = diag(Q1, Q2)^T v, is solved by its secular equation
+//   f(lambda) = 1 + rho sum_i z_i^2 / (d_i - lambda) = 0,
+// one root in each gap of the poles.  Entries with a negligible z_i, and one of two
+// poles closer than the tolerance (after a plane rotation that zeroes its z entry),
+// are deflated: they keep their pole as eigenvalue and their column of diag(Q1, Q2) as
+// eigenvector.  Each root is found as an offset tau from its nearer pole, so every
+// difference d_i - lambda_j = (d_i - d_origin) - tau is accurate; z is then recomputed
+// from the roots by Loewner's formula, which makes the eigenvectors
+// u_j = (zhat_i / (d_i - lambda_j))_i numerically orthogonal.  The new eigenvectors are
+// diag(Q1, Q2) [deflated columns | Q_k U] with one dense product.  Small blocks use the
+// QR iteration.
+
+static const int64_t kDcLeaf = 32;
+
+// Eigenpairs of a tridiagonal of order n <= kDcLeaf by the QR iteration: Z (n x n,
+// row-major, ldz) column j the eigenvector of d[j], d ascending.
+static bool dc_leaf(int64_t n, double *d, const double *e, double *Z, int64_t ldz) {
+    std::vector<double> dd(d, d + n), ee(n > 1 ? n - 1 : 0);
+    for (int64_t i = 0; i + 1 < n; ++i) ee[i] = e[i];
+    std::vector<Rot> rots;
+    if (!tridiag_qr(n, dd, ee, rots)) return false;
+    std::vector<double> Zt((size_t)n * n, 0.0);  // row k = column k of Z
+    for (int64_t i = 0; i < n; ++i) Zt[(size_t)i * n + i] = 1.0;
+    for (const Rot &r : rots) {
+        double *zk = &Zt[(size_t)r.k * n], *zn = &Zt[(size_t)(r.k + 1) * n];
+        for (int64_t i = 0; i < n; ++i) {
+            const double a = zk[i], b = zn[i];
+            zk[i] = r.c * a + r.s * b;
+            zn[i] = -r.s * a + r.c * b;
+        }
+    }
+    std::vector<int64_t> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return dd[a] < dd[b]; });
+    for (int64_t j = 0; j < n; ++j) {
+        d[j] = dd[order[j]];
+        for (int64_t i = 0; i < n; ++i) Z[i * ldz + j] = Zt[(size_t)order[j] * n + i];
+    }
+    return true;
+}
+
+// Root j of the secular equation with poles p[0] < ... < p[k-1], weights w = rho z^2
+// (all > 0): the root is found as origin + tau, origin its nearer pole; returns false
+// if the iteration does not settle.
+static bool secular_root(int64_t k, const double *p, const double *w, double rho, int64_t j,
+                         double &origin, double &tau) {
+    const double eps = std::numeric_limits<double>::epsilon();
+    const double lo = p[j], hi = j + 1 < k ? p[j + 1] : p[k - 1] + rho;
+    int64_t o = j;
+    if (j + 1 < k) {  // which half of the gap holds the root: f at the midpoint
+        const double mid = 0.5 * (lo + hi);
+        double f = 1.0;
+        for (int64_t i = 0; i < k; ++i) f += w[i] / (p[i] - mid);
+        if (f < 0.0) o = j + 1;
+    }
+    origin = p[o];
+    double a, b;  // bracket of tau: g(a) < 0 < g(b)
+    if (o == j) {
+        a = 0.0;
+        b = j + 1 < k ? 0.5 * (hi - lo) : rho;
+    } else {
+        a = -0.5 * (hi - lo);
+        b = 0.0;
+    }
+    std::vector<double> off(k);
+    for (int64_t i = 0; i < k; ++i) off[i] = p[i] - origin;
+    double t = 0.5 * (a + b);
+    for (int it = 0; it < 400; ++it) {
+        double g = 1.0, gp = 0.0;
+        for (int64_t i = 0; i < k; ++i) {
+            const double q = 1.0 / (off[i] - t);
+            g += w[i] * q;
+            gp += w[i] * q * q;
+        }
+        if (g == 0.0) break;
+        if (g < 0.0) a = t; else b = t;
+        if (b - a <= 2.0 * eps * std::max(std::fabs(a), std::fabs(b))) break;
+        double tn = t - g / gp;  // Newton; bisect when it leaves the bracket
+        if (!(tn > a && tn < b)) tn = 0.5 * (a + b);
+        if (tn == t) break;
+        t = tn;
+        if (it == 399) return false;
+    }
+    tau = t;
+    return true;
+}
+
+// C (n x k, ldc) = A (n x k, lda) B (k x k, ldb), rows in parallel, four at a time.
+static void dense_product(int64_t n, int64_t k, const double *A, int64_t lda, const double *B,
+                          int64_t ldb, double *C, int64_t ldc) {
+#pragma omp parallel for schedule(static) if (n * k * k >= 4000000)
+    for (int64_t i0 = 0; i0 < n; i0 += 4) {
+        const int64_t rows = std::min<int64_t>(4, n - i0);
+        for (int64_t r = 0; r < rows; ++r) std::fill(C + (i0 + r) * ldc, C + (i0 + r) * ldc + k, 0.0);
+        for (int64_t l = 0; l < k; ++l) {
+            const double *b = B + l * ldb;
+            for (int64_t r = 0; r < rows; ++r) {
+                const double a = A[(i0 + r) * lda + l];
+                if (a == 0.0) continue;
+                double *c = C + (i0 + r) * ldc;
+                for (int64_t j = 0; j < k; ++j) c[j] += a * b[j];
+            }
+        }
+    }
+}
+
+// Eigenpairs of the tridiagonal (d, e) of order n: eigenvalues ascending in d, the
+// eigenvectors in the columns of Z (n x n block of a row-major matrix with ldz).
+static bool dc_eig(int64_t n, double *d, double *e, double *Z, int64_t ldz) {
+    if (n <= kDcLeaf) return dc_leaf(n, d, e, Z, ldz);
+    const double eps = std::numeric_limits<double>::epsilon();
+    const int64_t m = n / 2;
+    const double beta = e[m - 1], rb = std::fabs(beta), sg = beta < 0 ? -1.0 : 1.0;
+    d[m - 1] -= rb;
+    d[m] -= rb;
+    for (int64_t i = 0; i < m; ++i) std::fill(Z + i * ldz + m, Z + i * ldz + n, 0.0);
+    for (int64_t i = m; i < n; ++i) std::fill(Z + i * ldz, Z + i * ldz + m, 0.0);
+    if (!dc_eig(m, d, e, Z, ldz)) return false;
+    if (!dc_eig(n - m, d + m, e + m, Z + m * ldz + m, ldz)) return false;
+    // z = diag(Q1, Q2)^T v: last row of Q1, sign(beta) times the first row of Q2
+    std::vector<double> z(n);
+    for (int64_t j = 0; j < m; ++j) z[j] = Z[(m - 1) * ldz + j];
+    for (int64_t j = m; j < n; ++j) z[j] = sg * Z[m * ldz + j];
+    double zn = 0.0;
+    for (double x : z) zn += x * x;
+    zn = std::sqrt(zn);
+    for (double &x : z) x /= zn;
+    const double rho = rb * zn * zn;
+    // poles in ascending order (columns of Z follow through `perm`)
+    std::vector<int64_t> perm(n);
+    std::iota(perm.begin(), perm.end(), 0);
+    std::stable_sort(perm.begin(), perm.end(), [&](int64_t a, int64_t b) { return d[a] < d[b]; });
+    std::vector<double> ds(n), zs(n);
+    for (int64_t i = 0; i < n; ++i) ds[i] = d[perm[i]], zs[i] = z[perm[i]];
+    double dmax = 0.0;
+    for (double x : ds) dmax = std::max(dmax, std::fabs(x));
+    const double tol = 8.0 * eps * std::max(dmax, rho);
+    // columns of diag(Q1, Q2) in pole order; deflating rotations act on them
+    std::vector<double> Q((size_t)n * n);
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < n; ++j) Q[(size_t)i * n + j] = Z[i * ldz + perm[j]];
+    std::vector<char> defl(n, 0);
+    for (int64_t i = 0; i < n; ++i)
+        if (rho * std::fabs(zs[i]) <= tol) defl[i] = 1;
+    int64_t prev = -1;
+    for (int64_t i = 0; i < n; ++i) {
+        if (defl[i]) continue;
+        if (prev >= 0 && ds[i] - ds[prev] <= tol) {
+            // rotate (prev, i) so that z[prev] = 0: prev deflates
+            const double r = std::hypot(zs[prev], zs[i]);
+            const double c = zs[i] / r, s = -zs[prev] / r;
+            zs[i] = r;
+            zs[prev] = 0.0;
+            const double dp = ds[prev], di = ds[i];
+            ds[prev] = c * c * dp + s * s * di;
+            ds[i] = s * s * dp + c * c * di;
+            for (int64_t row = 0; row < n; ++row) {
+                double *q = &Q[(size_t)row * n];
+                const double a = q[prev], b = q[i];
+                q[prev] = c * a + s * b;
+                q[i] = -s * a + c * b;
+            }
+            defl[prev] = 1;
+        }
+        prev = i;
+    }
+    std::vector<int64_t> keep;
+    for (int64_t i = 0; i < n; ++i)
+        if (!defl[i]) keep.push_back(i);
+    const int64_t k = (int64_t)keep.size();
+    std::vector<double> pk(k), wk(k), zk(k), lam(k), org(k), tau(k);
+    for (int64_t t = 0; t < k; ++t) {
+        pk[t] = ds[keep[t]];
+        zk[t] = zs[keep[t]];
+        wk[t] = rho * zk[t] * zk[t];
+    }
+    for (int64_t t = 0; t + 1 < k; ++t)
+        if (!(pk[t + 1] > pk[t])) return false;  // deflation keeps the poles apart
+    bool ok = true;
+#pragma omp parallel for schedule(dynamic, 8) if (k >= 128)
+    for (int64_t j = 0; j < k; ++j) {
+        if (!secular_root(k, pk.data(), wk.data(), rho, j, org[j], tau[j])) ok = false;
+        lam[j] = org[j] + tau[j];
+    }
+    if (!ok) return false;
+    // Loewner: zhat from the roots, pairing factors so that each ratio is at most one
+    std::vector<double> zh(k);
+#pragma omp parallel for schedule(static) if (k >= 128)
+    for (int64_t i = 0; i < k; ++i) {
+        auto diff = [&](int64_t j) { return (pk[i] - org[j]) - tau[j]; };  // d_i - lambda_j
+        double v = -diff(k - 1) / rho;
+        for (int64_t j = 0; j < i; ++j) v *= diff(j) / (pk[i] - pk[j]);
+        for (int64_t j = i; j + 1 < k; ++j) v *= diff(j) / (pk[i] - pk[j + 1]);
+        zh[i] = std::copysign(std::sqrt(std::fabs(v)), zk[i]);
+    }
+    // U (k x k): column j = (zhat_i / (d_i - lambda_j))_i, normalised
+    std::vector<double> U((size_t)k * k);
+#pragma omp parallel for schedule(static) if (k >= 128)
+    for (int64_t j = 0; j < k; ++j) {
+        double nrm = 0.0;
+        for (int64_t i = 0; i < k; ++i) {
+            const double u = zh[i] / ((pk[i] - org[j]) - tau[j]);
+            U[(size_t)i * k + j] = u;
+            nrm += u * u;
+        }
+        nrm = 1.0 / std::sqrt(nrm);
+        for (int64_t i = 0; i < k; ++i) U[(size_t)i * k + j] *= nrm;
+    }
+    // new eigenvectors: Q_k U for the roots, the deflated columns as they are
+    std::vector<double> Qk((size_t)n * k), QU((size_t)n * k);
+    for (int64_t row = 0; row < n; ++row)
+        for (int64_t t = 0; t < k; ++t) Qk[(size_t)row * k + t] = Q[(size_t)row * n + keep[t]];
+    dense_product(n, k, Qk.data(), k, U.data(), k, QU.data(), k);
+    // all eigenvalues with their source: root t (>= 0) or deflated column -(i + 1)
+    std::vector<std::pair<double, int64_t>> all;
+    all.reserve(n);
+    for (int64_t t = 0; t < k; ++t) all.push_back({lam[t], t});
+    for (int64_t i = 0; i < n; ++i)
+        if (defl[i]) all.push_back({ds[i], -(i + 1)});
+    std::stable_sort(all.begin(), all.end(),
+                     [](const std::pair<double, int64_t> &x, const std::pair<double, int64_t> &y) {
+                         return x.first < y.first;
+                     });
+    for (int64_t j = 0; j < n; ++j) {
+        d[j] = all[j].first;
+        const int64_t src = all[j].second;
+        for (int64_t row = 0; row < n; ++row)
+            Z[row * ldz + j] = src >= 0 ? QU[(size_t)row * k + src] : Q[(size_t)row * n + (-src - 1)];
+    }
+    return true;
+}
+
 // Consecutive Householder reflectors H_k = I - 2 v_k v_k^H (v_k unit, acting on
 // indices k+1..p-1; an empty v_k is the identity) grouped as
 //   H_k0 H_k0+1 ... H_k0+cnt-1 = I - Vb T Vb^H
@@ -471,12 +712,25 @@ static bool eigh_impl(int64_t p, const T *B, int64_t ldb, double *w, T *U, int64
         e[k] = ae;
         delta[k + 1] = ae > 0 ? delta[k] * (ek / ae) : delta[k];
     }
+    // eigenpairs of the tridiagonal: divide and conquer (Zd, eigenvalues ascending), or
+    // the QR iteration's recorded rotations where the blocks are small or the secular
+    // solver reports trouble
+    std::vector<double> Zd;
+    bool dc_ok = false;
+    if (p > kDcLeaf) {
+        std::vector<double> dd(d), ee(e);
+        Zd.assign((size_t)p * p, 0.0);
+        dc_ok = dc_eig(p, dd.data(), ee.data(), Zd.data(), p);
+        if (dc_ok) d = dd;
+    }
     std::vector<Rot> rots;
-    rots.reserve((size_t)2 * p * p);
-    if (!tridiag_qr(p, d, e, rots)) return false;
     std::vector<int64_t> order(p);
     std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return d[a] < d[b]; });
+    if (!dc_ok) {
+        rots.reserve((size_t)2 * p * p);
+        if (!tridiag_qr(p, d, e, rots)) return false;
+        std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return d[a] < d[b]; });
+    }
     // C = diag(delta) Z as a row-major p x p matrix.  Z = I J_1^T J_2^T ...: rotation
     // (k, c, s) replaces columns (z_k, z_{k+1}) by (c z_k + s z_{k+1}, -s z_k + c z_{k+1});
     // kept transposed (Zt row k = column k of Z) so each rotation is two row axpys,
@@ -489,19 +743,25 @@ static bool eigh_impl(int64_t p, const T *B, int64_t ldb, double *w, T *U, int64
     const std::vector<ReflBlock<T>> blocks = reflector_blocks(p, V);
 #pragma omp parallel if (p >= kParallelMin / 2)
     {
+        if (!dc_ok) {
 #pragma omp for schedule(dynamic)
-        for (int64_t ch = 0; ch < nchunks; ++ch) {
-            const int64_t i0 = ch * kChunk, i1 = std::min(p, i0 + kChunk);
-            for (int64_t i = i0; i < i1; ++i) Zt.row(i)[i] = 1.0;
-            if (i1 - i0 == kChunk)
-                rotate_columns<kChunk>(Zt, rots, i0, kChunk);
-            else
-                rotate_columns<0>(Zt, rots, i0, i1 - i0);
-        }
-        // C[r][jj] = delta[r] * Z[r][order[jj]] = delta[r] * Zt[order[jj]][r]
+            for (int64_t ch = 0; ch < nchunks; ++ch) {
+                const int64_t i0 = ch * kChunk, i1 = std::min(p, i0 + kChunk);
+                for (int64_t i = i0; i < i1; ++i) Zt.row(i)[i] = 1.0;
+                if (i1 - i0 == kChunk)
+                    rotate_columns<kChunk>(Zt, rots, i0, kChunk);
+                else
+                    rotate_columns<0>(Zt, rots, i0, i1 - i0);
+            }
+            // C[r][jj] = delta[r] * Z[r][order[jj]] = delta[r] * Zt[order[jj]][r]
 #pragma omp for schedule(static)
-        for (int64_t r = 0; r < p; ++r)
-            for (int64_t jj = 0; jj < p; ++jj) C.row(r)[jj] = delta[r] * Zt.row(order[jj])[r];
+            for (int64_t r = 0; r < p; ++r)
+                for (int64_t jj = 0; jj < p; ++jj) C.row(r)[jj] = delta[r] * Zt.row(order[jj])[r];
+        } else {
+#pragma omp for schedule(static)
+            for (int64_t r = 0; r < p; ++r)
+                for (int64_t jj = 0; jj < p; ++jj) C.row(r)[jj] = delta[r] * Zd[(size_t)r * p + jj];
+        }
 #pragma omp for schedule(dynamic)
         for (int64_t ch = 0; ch < nchunks; ++ch) {
             const int64_t j0 = ch * kChunk, j1 = std::min(p, j0 + kChunk), nc = j1 - j0;

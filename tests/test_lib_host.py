@@ -154,6 +154,39 @@ def test_host_eigh_degenerate_and_diagonal(cplx):
     assert np.allclose(w, [1, 2, 3])
 
 
+def _structured_spectra(p, rng, cplx):
+    """Matrices whose tridiagonal forms exercise every branch of the divide and conquer
+    step: deflation by a small z entry, by two close poles, graded and zero spectra."""
+    Q, _ = np.linalg.qr(rng.standard_normal((p, p)) + (1j * rng.standard_normal((p, p)) if cplx else 0))
+    out = {
+        "4-fold": np.repeat(rng.standard_normal(p // 4 + 1), 4)[:p],
+        "cluster 1e-14": 1.0 + 1e-14 * rng.standard_normal(p),
+        "graded": np.logspace(-15, 0, p),
+        "converged Ritz window": np.concatenate([np.linspace(7.0, 7.1, p // 2),
+                                                 1e-6 * rng.standard_normal(p - p // 2)]),
+    }
+    mats = {k: (Q * lam) @ Q.conj().T for k, lam in out.items()}
+    mats["1D Laplacian"] = 2 * np.eye(p) - np.eye(p, k=1) - np.eye(p, k=-1)
+    mats["Wilkinson"] = np.diag(np.abs(np.arange(p) - p // 2).astype(float)) + np.eye(p, k=1) + np.eye(p, k=-1)
+    mats["ones"] = np.ones((p, p))
+    mats["zero"] = np.zeros((p, p))
+    return mats
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+@pytest.mark.parametrize("p", [33, 130])
+def test_host_eigh_structured_spectra(cplx, p):
+    # sizes above 32 take divide and conquer: 33 one merge of two leaves, 130 two levels
+    # of merges; each case against numpy and for orthogonality and residual
+    for name, B in _structured_spectra(p, np.random.default_rng(p), cplx).items():
+        w, U = afsi.afsi_host_eigh(B)
+        wr = np.linalg.eigvalsh(B)
+        scale = max(1e-300, np.max(np.abs(wr)))
+        assert np.max(np.abs(w - wr)) <= 1e-13 * max(scale, 1.0) * max(1, p / 32), name
+        assert np.max(np.abs(U.conj().T @ U - np.eye(p))) <= 1e-13 * max(1, p / 10), name
+        assert np.max(np.abs(B @ U - U * w)) <= 1e-13 * max(scale, 1.0) * max(1, p / 32), name
+
+
 @pytest.mark.parametrize("cplx", [False, True])
 def test_host_eigh_rejects_non_finite_input(cplx):
     B = np.eye(6, dtype=np.complex128 if cplx else np.float64)
