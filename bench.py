@@ -27,6 +27,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# pencil side of the grid ordering (afsi_grid_order): 25 x 25 tiles put the +-x neighbours
+# 625 rows away, so the products run each XCD on rows 76 apart (the matrix's median row
+# reach / 8) and reuse those rows from its L2; 20-50 measured within 2% of each other
+PENCIL = 25
 
 
 def log(msg):
@@ -79,6 +83,11 @@ def main():
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=0)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--order", choices=["pencil", "natural"], default="pencil",
+                    help="row order of a grid workload: the 25 x 25 pencil ordering of afsi_grid_order "
+                         "(default) or the natural one")
+    ap.add_argument("--no-natural", action="store_true",
+                    help="skip the natural-order comparison steps (profiling runs)")
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run three plain device copies of one block (counter calibration)")
@@ -152,7 +161,18 @@ def main():
     cplx = A.is_complex
     log(f"workload {cfg.name}: n={n} nnz={A.nnz} p={p} k={k} bounds=({lmin:.4g},{lmax:.4g}) "
         f"interval=({a:.6g},{b:.6g}) gen {time.time() - t0:.1f}s")
-    M = afsi.Matrix(A, device=0, bounds=(lmin, lmax))
+    # grid workloads run in the pencil ordering (P A P^T; afsi_grid_order, afsi_csr_permute):
+    # same spectrum, start block moved to the same order
+    gsize = args.size or cfg.size
+    order = args.order if cfg.extra.get("grid") == 3 else "natural"
+    perm = None
+    A_run = A
+    if order == "pencil":
+        perm = afsi.afsi_grid_order(gsize, gsize, gsize, PENCIL, PENCIL)
+        A_run = afsi.afsi_csr_permute(A, perm)
+        log(f"pencil ordering {PENCIL} x {PENCIL}: median row reach {PENCIL * PENCIL}")
+    M = afsi.Matrix(A_run, device=0, bounds=(lmin, lmax))
+    mh = [M.handle]   # the matrix the timed steps use
     coeffs = afsi.afsi_filter_coefficients(lmin, lmax, a, b, k, cfg.damping)
     X0 = start_block(n, p, seed=0, complex_=cplx)
     f64 = torch.complex128 if cplx else torch.float64
@@ -161,6 +181,9 @@ def main():
     B0 = torch.from_numpy(X0).to(dev)
     del X0
     B1, B2 = torch.empty_like(B0), torch.empty_like(B0)
+    if perm is not None:
+        afsi.afsi_permute_rows(B0, perm, B1)
+        B0.copy_(B1)
     F0 = torch.empty((n, p), dtype=f32, device=dev)    # filter blocks of the mixed form
     F1, F2 = torch.empty_like(F0), torch.empty_like(F0)
     stream = torch.cuda.current_stream()
@@ -185,10 +208,10 @@ def main():
 
     def run_filter(deg):
         if cur_form[0] == "fp64":
-            ms, kind = afsi.afsi_filter_block_profiled(M.handle, coeffs, deg, B0, B1, B2)
+            ms, kind = afsi.afsi_filter_block_profiled(mh[0], coeffs, deg, B0, B1, B2)
         else:
             afsi.afsi_convert_block(B0, F0)
-            ms, kind = afsi.afsi_filter_block_profiled(M.handle, coeffs, deg, F0, F1, F2)
+            ms, kind = afsi.afsi_filter_block_profiled(mh[0], coeffs, deg, F0, F1, F2)
             afsi.afsi_convert_block(F1, B1)
         steady_ms.extend(ms[2:][kind[2:] == 3].tolist())
 
@@ -203,7 +226,7 @@ def main():
         ev[1].record(stream)
         afsi.afsi_orthonormalize(None, B1, B2)
         ev[2].record(stream)
-        ritz = afsi.afsi_rayleigh_ritz(M.handle, B1, B0, B2)
+        ritz = afsi.afsi_rayleigh_ritz(mh[0], B1, B0, B2)
         ev[3].record(stream)
         res = afsi.afsi_residual_norms(B0, B2, ritz)
         ev[4].record(stream)
@@ -260,6 +283,32 @@ def main():
     cur_form[0] = args.form
     del F0, F1, F2
 
+    # the same iteration on the matrix in its natural order (the ordering's effect)
+    natural_rec = None
+    if perm is not None and not args.no_natural:
+        Mn = afsi.Matrix(A, device=0, bounds=(lmin, lmax))
+        mh[0] = Mn.handle
+        step()
+        torch.cuda.synchronize()
+        steady_ms.clear()
+        filt_ms.clear()
+        phase_ms.clear()
+        t2 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        nat_step = 1e3 * (time.perf_counter() - t2) / args.steps
+        nat_k1 = float(np.mean(steady_ms))
+        natural_rec = {"ms_per_step": round(nat_step, 3), "value": round(fbytes / (nat_step * 1e-3) / 1e9, 2),
+                       "filter_ms": round(float(np.median(filt_ms)), 3),
+                       "dominant_launch_us": round(nat_k1 * 1e3, 2),
+                       "dominant_frac": round(steady_bytes / (nat_k1 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                       "pencil_speedup_step": round(nat_step / ms_per_step, 3),
+                       "pencil_speedup_dominant": round(nat_k1 / steady_launch_ms, 3)}
+        log(f"natural order: {natural_rec}")
+        mh[0] = M.handle
+        Mn.close()
+
     # measured copy bandwidth: a plain device copy of one block, same stream, HIP events
     for _ in range(2):
         B2.copy_(B1)
@@ -283,7 +332,7 @@ def main():
         f"device copy {copy_gbs:.0f} GB/s; 3-read/1-write pass {stream3_gbs:.0f} GB/s")
 
     traffic = None
-    tpath = os.path.join(ROOT, "profiles", f"traffic_{cfg.name}_{args.form}.json")
+    tpath = os.path.join(ROOT, "profiles", f"traffic_{cfg.name}_{order}_{args.form}.json")
     if os.path.exists(tpath):
         rec = json.load(open(tpath))
         if rec.get("kernel_source_sha1") == kernel_source_sha1():
@@ -308,12 +357,15 @@ def main():
             "workload": cfg.name,
             "description": cfg.description,
             "n": n, "nnz": A.nnz, "p": p, "degree": k, "damping": cfg.damping, "form": args.form,
+            "ordering": (f"pencil {PENCIL}x{PENCIL} (afsi_grid_order: P A P^T, same spectrum)"
+                         if perm is not None else "natural"),
             "step": f"one solver iteration: filter ({k} products) + CholQR2 + Rayleigh-Ritz + residuals",
         },
         "pct_hbm_peak": round(100.0 * value / HBM_PEAK_GBS, 2),
         "filter_only_gbs": round(filter_gbs, 1),
         "filter_ms": round(filt_med, 3),
         "other_form": other_rec,
+        "natural_order": natural_rec,
         "phase_ms": {"filter": round(filt_med, 3), "orthonormalize": round(orth_ms, 3),
                      "rayleigh_ritz": round(rr_ms, 3), "residuals": round(res_ms, 3)},
         "measured_copy_gbs": round(copy_gbs, 1),
@@ -524,6 +576,8 @@ def batched_record(afsi, torch, dev, groups=16, cols=96, launches=30):
     from workloads.stream import slice_intervals
 
     A, (lo, hi), _, cfg = build_config("lap3d_pot_100", seed=0)
+    # in the pencil ordering, as the main iteration (random blocks need no reordering)
+    A = afsi.afsi_csr_permute(A, afsi.afsi_grid_order(cfg.size, cfg.size, cfg.size, PENCIL, PENCIL))
     M = afsi.Matrix(A, device=0, bounds=(lo, hi))
     k = cfg.degree
     l1, l2 = 2.0 / (hi - lo), -(hi + lo) / (hi - lo)

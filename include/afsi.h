@@ -111,6 +111,47 @@ int afsi_matrix_destroy(afsi_matrix_t A);
  */
 int afsi_matrix_set_column_block(afsi_matrix_t A, int64_t bytes);
 int afsi_matrix_get_column_block(afsi_matrix_t A, int64_t *bytes);
+/*
+ * Locality ordering of the unknowns (host-side; Section 3.3.1: the filter's cost is the
+ * SpMM, and its speed is set by how often the gathered rows of the dense operand are
+ * found in cache).  The eigenvalues of P A P^T are those of A and its eigenvectors are
+ * P times A's, so a solve may run on a reordered matrix with blocks in the new order.
+ *
+ * afsi_grid_order: the pencil ordering of an nx x ny x nz grid whose natural row index is
+ * (x ny + y) nz + z.  The (y, z) plane is cut into tiles of ty x tz points (the last tile
+ * of a side may be smaller); tiles are taken one after another (y tiles outer), and each
+ * tile runs along all of x with its (y, z) points in natural order at every x.  Then the
+ * +-x neighbours of a point sit ty tz rows away, so for a 7-point stencil almost every
+ * neighbour lies within a constant row distance (the tile's cross-section) instead of
+ * ny nz rows; the products pick that distance up from the matrix and run each XCD on
+ * rows that many positions apart, keeping the reused rows in its own L2.  Writes
+ * perm[new] = old for all nx ny nz points (caller-allocated host array).
+ * AFSI_E_INVALID for negative sizes or tiles smaller than 1.
+ */
+int afsi_grid_order(int64_t nx, int64_t ny, int64_t nz, int64_t ty, int64_t tz, int64_t *perm);
+
+/*
+ * B = P A P^T in CSR on the host: B[i][j] = A[perm[i]][perm[j]], i.e. row i of B is row
+ * perm[i] of A with column c renamed to the position of c in perm, entries sorted by the
+ * new column.  Same array formats as afsi_matrix_create_csr (which then takes B);
+ * outputs are caller-allocated: out_row_ptr[n+1], out_col_idx[nnz], out_vals[nnz].
+ * perm must hold each of 0..n-1 exactly once (AFSI_E_INVALID otherwise, and for the
+ * structural violations afsi_matrix_create_csr rejects).
+ */
+int afsi_csr_permute(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col_idx,
+                     const void *vals, int32_t val_dtype, const int64_t *perm, int64_t *out_row_ptr,
+                     int32_t *out_col_idx, void *out_vals);
+
+/*
+ * Device row permutation of a block: dst row i = src row perm[i] (inverse = 0: a block
+ * in A's order to P A P^T's), or dst row perm[i] = src row i (inverse != 0: back).
+ * perm: host array of src->rows entries holding each of 0..rows-1 once (validated,
+ * then copied to the device on `stream`); src and dst: same shape and dtype, not
+ * overlapping.  Synchronises `stream`.
+ */
+int afsi_permute_rows(const afsi_block *src, const int64_t *perm, int32_t inverse, afsi_block *dst,
+                      void *stream);
+
 /* n, nnz, value dtype (AFSI_R64 or AFSI_C128), device ordinal. Any output may be NULL. */
 int afsi_matrix_info(afsi_matrix_t A, int64_t *n, int64_t *nnz, int32_t *dtype, int32_t *device);
 

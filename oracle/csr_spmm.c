@@ -4,14 +4,16 @@
  * against.  Computes C = A * B for a square CSR matrix A (n x n) and a row-major
  * dense block B (n x p, leading dimension p); the textbook row-wise CSR product
  * that Section 3.3.1 takes as its starting point.  One OpenMP loop over rows,
- * no blocking, no reordering of the per-row sum.
+ * no blocking, no reordering of the per-row sum.  Small products run on one thread
+ * (a team costs more than it saves there, and far more on a loaded host); the
+ * threading never changes a result.
  */
 #include <stdint.h>
 
 void oracle_spmm_f64(int64_t n, const int64_t *row_ptr, const int32_t *col,
                      const double *val, const double *B, int64_t p, double *C)
 {
-    #pragma omp parallel for schedule(static)
+    #pragma omp parallel for schedule(static) if (n * p >= 65536)
     for (int64_t i = 0; i < n; ++i) {
         double *c = C + i * p;
         for (int64_t t = 0; t < p; ++t) c[t] = 0.0;
@@ -27,7 +29,7 @@ void oracle_spmm_f64(int64_t n, const int64_t *row_ptr, const int32_t *col,
 void oracle_spmm_c128(int64_t n, const int64_t *row_ptr, const int32_t *col,
                       const double *val, const double *B, int64_t p, double *C)
 {
-    #pragma omp parallel for schedule(static)
+    #pragma omp parallel for schedule(static) if (n * p >= 32768)
     for (int64_t i = 0; i < n; ++i) {
         double *c = C + 2 * i * p;
         for (int64_t t = 0; t < 2 * p; ++t) c[t] = 0.0;

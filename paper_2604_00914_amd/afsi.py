@@ -126,6 +126,9 @@ _SIGS = {
     "afsi_residual_norms_noalloc": (C.c_int, [_BP, _BP, _P, _P, _P]),
     "afsi_convert_block": (C.c_int, [_BP, _BP, _P]),
     "afsi_gather_columns": (C.c_int, [_BP, _P, C.c_int64, _BP, _P]),
+    "afsi_permute_rows": (C.c_int, [_BP, _P, C.c_int32, _BP, _P]),
+    "afsi_grid_order": (C.c_int, [C.c_int64, C.c_int64, C.c_int64, C.c_int64, C.c_int64, _P]),
+    "afsi_csr_permute": (C.c_int, [C.c_int64, C.c_int64, _P, _P, _P, C.c_int32, _P, _P, _P, _P]),
     "afsi_select_degree": (C.c_int, [_P, C.c_int64, C.c_int64, _P, C.c_int, C.c_double, C.c_double, C.c_double, C.POINTER(C.c_int)]),
     "afsi_lock_select": (C.c_int, [_P, C.c_int64, _P, _P, C.c_double, C.c_double, C.c_double, C.c_int64, _I64P, _P, C.POINTER(C.c_int)]),
     "afsi_host_eigh": (C.c_int, [C.c_int64, C.c_int32, _P, C.c_int64, _P, _P, C.c_int64]),
@@ -411,6 +414,37 @@ def afsi_convert_block(src, dst, stream=None):
 def afsi_gather_columns(src, cols, dst, stream=None):
     c = _np(cols, np.int32)
     _check(lib().afsi_gather_columns(_bref(_blk(src)), _ptr(c), c.size, _bref(_blk(dst)), _stream(stream)))
+
+
+def afsi_permute_rows(src, perm, dst, inverse: bool = False, stream=None):
+    """dst row i = src row perm[i]; with inverse, dst row perm[i] = src row i."""
+    pm = _np(perm, np.int64)
+    _check(lib().afsi_permute_rows(_bref(_blk(src)), _ptr(pm), int(bool(inverse)), _bref(_blk(dst)), _stream(stream)))
+
+
+def afsi_grid_order(nx: int, ny: int, nz: int, ty: int, tz: int) -> np.ndarray:
+    """Pencil ordering of an nx x ny x nz grid (perm[new] = old)."""
+    perm = np.empty(max(0, nx * ny * nz), dtype=np.int64)
+    _check(lib().afsi_grid_order(nx, ny, nz, ty, tz, _ptr(perm)))
+    return perm
+
+
+def afsi_csr_permute(csr, perm):
+    """P A P^T of a CSR (workloads.CSR fields n, row_ptr, col, val) as a new CSR."""
+    from workloads.matrices import CSR
+
+    cplx = np.iscomplexobj(csr.val)
+    rp = _np(csr.row_ptr, np.int64)
+    ci = _np(csr.col, np.int32)
+    v = _np(csr.val, np.complex128 if cplx else np.float64)
+    pm = _np(perm, np.int64)
+    n, nnz = int(csr.n), int(rp[-1])
+    orp = np.empty(n + 1, dtype=np.int64)
+    oci = np.empty(nnz, dtype=np.int32)
+    ov = np.empty(nnz, dtype=v.dtype)
+    _check(lib().afsi_csr_permute(n, nnz, _ptr(rp), _ptr(ci), _ptr(v), C128 if cplx else R64, _ptr(pm),
+                                  _ptr(orp), _ptr(oci), _ptr(ov)))
+    return CSR(n, orp, oci, ov)
 
 
 def afsi_select_degree(ritz, e: int, coeffs, l1: float, l2: float, tau_a: float) -> int:

@@ -1075,6 +1075,98 @@ int afsi_gather_columns(const afsi_block *src, const int32_t *cols, int64_t coun
     });
 }
 
+// perm must hold each of 0..n-1 once
+static void check_permutation(const int64_t *perm, int64_t n) {
+    AFSI_REQUIRE(n == 0 || perm != nullptr, "perm is NULL");
+    std::vector<char> seen(n, 0);
+    for (int64_t i = 0; i < n; ++i) {
+        AFSI_REQUIRE(perm[i] >= 0 && perm[i] < n, "perm[%lld] = %lld out of range", (long long)i,
+                     (long long)perm[i]);
+        AFSI_REQUIRE(!seen[perm[i]], "perm repeats %lld", (long long)perm[i]);
+        seen[perm[i]] = 1;
+    }
+}
+
+int afsi_permute_rows(const afsi_block *src, const int64_t *perm, int32_t inverse, afsi_block *dst,
+                      void *stream) {
+    return guarded([&] {
+        check_block(src, "src");
+        check_block(dst, "dst");
+        AFSI_REQUIRE(src->rows == dst->rows && src->cols == dst->cols && src->dtype == dst->dtype,
+                     "dst must have src's shape and dtype");
+        AFSI_REQUIRE(!overlap(src, dst), "src and dst overlap");
+        check_permutation(perm, src->rows);
+        if (src->rows == 0 || src->cols == 0) return;
+        hipStream_t s = as_stream(stream);
+        Workspace &ws = workspace(s);
+        int64_t *d = (int64_t *)ws.dev_reserve(SLOT_GATHER, sizeof(int64_t) * src->rows);
+        AFSI_HIP(hipMemcpyAsync(d, perm, sizeof(int64_t) * src->rows, hipMemcpyHostToDevice, s));
+        launch_permute_rows(*src, d, inverse != 0, *dst, s);
+        AFSI_HIP(hipStreamSynchronize(s));
+    });
+}
+
+int afsi_grid_order(int64_t nx, int64_t ny, int64_t nz, int64_t ty, int64_t tz, int64_t *perm) {
+    return guarded([&] {
+        AFSI_REQUIRE(nx >= 0 && ny >= 0 && nz >= 0, "negative grid size");
+        AFSI_REQUIRE(ty >= 1 && tz >= 1, "tile sides must be at least 1");
+        const int64_t n = nx * ny * nz;
+        AFSI_REQUIRE(n == 0 || perm != nullptr, "perm is NULL");
+        // pencils: ty x tz tiles of the (y, z) plane, one after another (y tile outer), each
+        // running along x with its (y, z) points in natural order at every x
+        int64_t k = 0;
+        for (int64_t y0 = 0; y0 < ny; y0 += ty)
+            for (int64_t z0 = 0; z0 < nz; z0 += tz)
+                for (int64_t x = 0; x < nx; ++x)
+                    for (int64_t y = y0; y < std::min(ny, y0 + ty); ++y)
+                        for (int64_t z = z0; z < std::min(nz, z0 + tz); ++z)
+                            perm[k++] = (x * ny + y) * nz + z;
+    });
+}
+
+int afsi_csr_permute(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col_idx,
+                     const void *vals, int32_t val_dtype, const int64_t *perm, int64_t *out_row_ptr,
+                     int32_t *out_col_idx, void *out_vals) {
+    return guarded([&] {
+        AFSI_REQUIRE(n >= 0 && nnz >= 0, "negative size");
+        AFSI_REQUIRE(n < (1LL << 31), "n must be below 2^31");
+        AFSI_REQUIRE(val_dtype == AFSI_R64 || val_dtype == AFSI_C128,
+                     "values must be R64 or C128 (got %d)", val_dtype);
+        AFSI_REQUIRE(row_ptr && out_row_ptr, "row_ptr / out_row_ptr is NULL");
+        AFSI_REQUIRE(nnz == 0 || (col_idx && vals && out_col_idx && out_vals), "NULL array");
+        AFSI_REQUIRE(row_ptr[0] == 0 && row_ptr[n] == nnz, "row_ptr must start at 0 and end at nnz");
+        check_permutation(perm, n);
+        std::vector<int32_t> inv(n);
+        for (int64_t i = 0; i < n; ++i) inv[perm[i]] = (int32_t)i;
+        out_row_ptr[0] = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            const int64_t r = perm[i];
+            AFSI_REQUIRE(row_ptr[r + 1] >= row_ptr[r], "row_ptr decreases at row %lld", (long long)r);
+            out_row_ptr[i + 1] = out_row_ptr[i] + (row_ptr[r + 1] - row_ptr[r]);
+        }
+        const size_t eb = (size_t)elem_bytes(val_dtype);
+        const char *v = (const char *)vals;
+        char *ov = (char *)out_vals;
+        std::vector<std::pair<int32_t, int64_t>> row;
+        for (int64_t i = 0; i < n; ++i) {
+            // row i of P A P^T is row perm[i] of A, columns renamed by the inverse
+            // permutation and sorted
+            const int64_t r = perm[i], e0 = row_ptr[r], len = row_ptr[r + 1] - e0, o = out_row_ptr[i];
+            row.resize(len);
+            for (int64_t t = 0; t < len; ++t) {
+                const int32_t c = col_idx[e0 + t];
+                AFSI_REQUIRE(c >= 0 && c < n, "column %d out of range in row %lld", c, (long long)r);
+                row[t] = {inv[c], e0 + t};
+            }
+            std::sort(row.begin(), row.end());
+            for (int64_t t = 0; t < len; ++t) {
+                out_col_idx[o + t] = row[t].first;
+                std::memcpy(ov + (size_t)(o + t) * eb, v + (size_t)row[t].second * eb, eb);
+            }
+        }
+    });
+}
+
 int afsi_select_degree(const double *ritz, int64_t p, int64_t e, const double *coeffs, int kmax,
                        double l1, double l2, double tau_a, int *degree_out) {
     return guarded([&] {

@@ -209,6 +209,10 @@ void launch_convert(const afsi_block &src, const afsi_block &dst, hipStream_t s)
 void launch_gather_columns(const afsi_block &src, const int32_t *d_cols, int64_t count,
                            const afsi_block &dst, hipStream_t s);
 void launch_to_f32(const double *src, float *dst, int64_t count, hipStream_t s);
+// dst row i = src row d_perm[i], or with `inverse` dst row d_perm[i] = src row i (d_perm a
+// device permutation of src.rows rows; same dtype and shape).
+void launch_permute_rows(const afsi_block &src, const int64_t *d_perm, bool inverse,
+                         const afsi_block &dst, hipStream_t s);
 
 // ---------------------------------------------------------------- kernels (dense.hip)
 

@@ -15,8 +15,9 @@
 //        X stored transposed so operand reads are conflict-free.  Column tiles of a
 //        row tile are adjacent in the grid, so X rows are reused from cache.  For an
 //        upper-triangular M (R^{-1}) a column tile stops at its last column's row.
-// A Gram product with X == Y takes its lower triangle from the upper one in the
-// chunk reduction, so the Cholesky-QR Gram is exactly Hermitian.
+// A Gram product with X == Y computes only the tiles that reach the diagonal or above
+// it and takes its lower triangle from the upper one in the chunk reduction, so the
+// Cholesky-QR Gram is exactly Hermitian.
 // Complex Hermitian blocks use real views: a complex n x p block with leading
 // dimension ld is a real n x 2p block with leading dimension 2 ld, and
 //   X^H Y = (Gr[2i,2j] + Gr[2i+1,2j+1]) + i (Gr[2i,2j+1] - Gr[2i+1,2j])  with Gr = Xr^T Yr,
@@ -68,18 +69,23 @@ __global__ __launch_bounds__(256) void gram_f64_kernel(const double *__restrict_
                                                        const double *__restrict__ Y, int64_t ldy,
                                                        int64_t n, int p, int q,
                                                        int64_t rows_per_chunk, int nchunks,
-                                                       double *__restrict__ ws) {
+                                                       bool upper_only, double *__restrict__ ws) {
     __shared__ __align__(16) double Xs[2][BK][PADM];
     __shared__ __align__(16) double Ys[2][BK][PADN];
-    const int tiles_j = (q + BN - 1) / BN;
-    const int tiles = ((p + BM - 1) / BM) * tiles_j;
+    const int tiles_i = (p + BM - 1) / BM, tiles_j = (q + BN - 1) / BN;
+    // upper_only: only tiles holding an entry on or above the diagonal (row tile ti
+    // with ti BM < (tj + 1) BN), column tile by column tile
+    auto col_tiles = [&](int tj) { return upper_only ? min(tiles_i, ((tj + 1) * BN + BM - 1) / BM) : tiles_i; };
+    int tiles = 0;
+    for (int tj = 0; tj < tiles_j; ++tj) tiles += col_tiles(tj);
     // workgroup b runs on XCD b % 8: all tiles of one row chunk go to the same XCD
     // (consecutive slots there), so the chunk's rows come from HBM once and the other
     // tiles read them from that XCD's L2
     const int slot = blockIdx.x >> 3;
     const int chunk = (slot / tiles) * 8 + (blockIdx.x & 7);
     if (chunk >= nchunks) return;
-    const int ti = (slot % tiles) / tiles_j, tj = (slot % tiles) % tiles_j;
+    int ti = slot % tiles, tj = 0;
+    while (ti >= col_tiles(tj)) ti -= col_tiles(tj++);
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int wr = w >> 1, wc = w & 1;
     const int i0 = ti * BM, j0 = tj * BN;
@@ -325,11 +331,13 @@ static bool aligned_pairs(const double *base, int64_t ld, int64_t rows, int64_t 
 
 static void gram_raw(const double *X, int64_t ldx, const double *Y, int64_t ldy, int64_t n,
                      int64_t p, int64_t q, double *G, int64_t ldg, int slot, hipStream_t s) {
-    // X == Y: every tile is still computed (dropping the lower ones left the XCDs
-    // unevenly loaded), and the reduction mirrors the upper triangle so that G is
-    // exactly Hermitian
+    // X == Y: tiles strictly below the diagonal are skipped and the reduction mirrors
+    // the upper triangle, so that G is exactly Hermitian; the chunks are sized by the
+    // tiles that run, so every XCD still holds one full resident round
     const bool sym = X == Y && ldx == ldy && p == q;
-    const int64_t ti = (p + BM - 1) / BM, tj = (q + BN - 1) / BN, tiles = ti * tj;
+    const int64_t ti = (p + BM - 1) / BM, tj = (q + BN - 1) / BN;
+    int64_t tiles = 0;
+    for (int64_t j = 0; j < tj; ++j) tiles += sym ? std::min(ti, ((j + 1) * BN + BM - 1) / BM) : ti;
     // chunks: a multiple of 8 (one per XCD in turn) with at most one resident round
     // of workgroups per XCD, and at least 512 rows each
     const int64_t per_xcd = std::max<int64_t>(1, kGramResidentPerXcd / tiles);
@@ -343,7 +351,8 @@ static void gram_raw(const double *X, int64_t ldx, const double *Y, int64_t ldy,
     AFSI_REQUIRE(grid < (1LL << 31), "Gram product too large");
     const bool vec = aligned_pairs(X, ldx, n, p) && aligned_pairs(Y, ldy, n, q);
     hipLaunchKernelGGL(vec ? gram_f64_kernel<true> : gram_f64_kernel<false>, dim3((unsigned)grid),
-                       dim3(256), 0, s, X, ldx, Y, ldy, n, (int)p, (int)q, rows, (int)nchunks, ws);
+                       dim3(256), 0, s, X, ldx, Y, ldy, n, (int)p, (int)q, rows, (int)nchunks, sym,
+                       ws);
     hipLaunchKernelGGL(reduce_chunks_kernel, dim3((unsigned)((p * q + 255) / 256)), dim3(256), 0, s,
                        ws, (int)nchunks, (int)p, (int)q, sym, G, ldg);
     AFSI_HIP(hipGetLastError());

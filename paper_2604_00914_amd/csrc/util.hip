@@ -1,4 +1,5 @@
-// Bandwidth kernels: precision conversion of blocks and matrix values, column gather.
+// Bandwidth kernels: precision conversion of blocks and matrix values, column gather,
+// row permutation.
 #include "internal.h"
 
 namespace afsi {
@@ -22,6 +23,20 @@ __global__ void gather_kernel(const T *__restrict__ src, int64_t lds, const int3
     const int64_t i = idx / per_row, r = idx % per_row;
     const int64_t t = r / comp, c = r % comp;
     dst[(i * ldd + t) * comp + c] = src[(i * lds + cols[t]) * comp + c];
+}
+
+// Row permutation: dst row i = src row perm[i] (gather) or dst row perm[i] = src row i
+// (inverse: scatter), U the widest unit that divides every row, ld and base.
+template <class U>
+__global__ void permute_rows_kernel(const U *__restrict__ src, int64_t lds, U *__restrict__ dst,
+                                    int64_t ldd, const int64_t *__restrict__ perm, int inverse,
+                                    int64_t rows, int64_t units) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= rows * units) return;
+    const int64_t i = idx / units, c = idx % units;
+    const int64_t pi = perm[i];
+    const int64_t si = inverse ? i : pi, di = inverse ? pi : i;
+    dst[di * ldd + c] = src[si * lds + c];
 }
 
 __global__ void to_f32_kernel(const double *__restrict__ src, float *__restrict__ dst, int64_t count) {
@@ -115,6 +130,30 @@ void launch_gather_columns(const afsi_block &src, const int32_t *d_cols, int64_t
         hipLaunchKernelGGL((gather_kernel<float>), dim3(blocks_for(tot)), dim3(256), 0, s,
                            (const float *)src.ptr, src.ld, d_cols, count, comp, (float *)dst.ptr,
                            dst.ld, src.rows);
+    AFSI_HIP(hipGetLastError());
+}
+
+void launch_permute_rows(const afsi_block &src, const int64_t *d_perm, bool inverse,
+                         const afsi_block &dst, hipStream_t s) {
+    const int64_t eb = elem_bytes(src.dtype);
+    const int64_t row = src.cols * eb, lds = src.ld * eb, ldd = dst.ld * eb;
+    if (src.rows == 0 || row == 0) return;
+    const uintptr_t a = reinterpret_cast<uintptr_t>(src.ptr) | reinterpret_cast<uintptr_t>(dst.ptr);
+    auto fits = [&](int64_t u) { return row % u == 0 && lds % u == 0 && ldd % u == 0 && a % u == 0; };
+    const int64_t u = fits(16) ? 16 : (fits(8) ? 8 : 4);
+    const int64_t units = row / u, tot = src.rows * units;
+    if (u == 16)
+        hipLaunchKernelGGL((permute_rows_kernel<uint4>), dim3(blocks_for(tot)), dim3(256), 0, s,
+                           (const uint4 *)src.ptr, lds / 16, (uint4 *)dst.ptr, ldd / 16, d_perm,
+                           (int)inverse, src.rows, units);
+    else if (u == 8)
+        hipLaunchKernelGGL((permute_rows_kernel<uint2>), dim3(blocks_for(tot)), dim3(256), 0, s,
+                           (const uint2 *)src.ptr, lds / 8, (uint2 *)dst.ptr, ldd / 8, d_perm,
+                           (int)inverse, src.rows, units);
+    else
+        hipLaunchKernelGGL((permute_rows_kernel<uint32_t>), dim3(blocks_for(tot)), dim3(256), 0, s,
+                           (const uint32_t *)src.ptr, lds / 4, (uint32_t *)dst.ptr, ldd / 4, d_perm,
+                           (int)inverse, src.rows, units);
     AFSI_HIP(hipGetLastError());
 }
 

@@ -91,6 +91,7 @@ CONFIGS = {
         complex_=False,
         filter_dtypes=("f64", "f32"),
         interval=_centred(1.39e-3),
+        extra={"grid": 3},  # a cube grid of size^3 points, natural row index (x N + y) N + z
     ),
     "lap3d_pot_27": WorkloadConfig(
         name="lap3d_pot_27",
@@ -103,6 +104,7 @@ CONFIGS = {
         complex_=False,
         filter_dtypes=("f64", "f32"),
         interval=_centred(200.0 / (0.1435 * 27 ** 3)),
+        extra={"grid": 3},  # a cube grid of size^3 points, natural row index (x N + y) N + z
     ),
     "tb3d_64": WorkloadConfig(
         name="tb3d_64",
