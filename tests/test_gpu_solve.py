@@ -251,3 +251,37 @@ def test_sensitivity_modes_match_oracle(mode, value):
     assert np.max(np.abs(lam - ref.eigenvalues)) <= 1e-10 * hi
     assert abs(r.iterations - ref.iterations) <= 2
     assert abs(r.avg_degree - ref.avg_degree) <= 2.0
+
+
+def _tau6_fixture(seed):
+    import os
+
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        f"lap3d_pot_27_tau1e-6_seed{seed}.txt")
+    head = [l for l in open(path) if l.startswith("#")]
+    count = int(head[2].split()[2])
+    vals = np.array([float(l) for l in open(path) if l.strip() and not l.startswith("#")])
+    assert vals.size == count
+    return vals
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3, 4])
+def test_lap3d27_fixed_degree_tau6_matches_oracle(seed):
+    # the fixed-degree (Jackson 120, p = 360) tau_c = 1e-6 mode of the 27^3 workload,
+    # against the oracle's Algorithm 4 from the same start block (stored fixtures): the
+    # same count (seed 2: both stop with 195 of the 196 eigenvalues, the one 4.9e-5 inside
+    # b set aside by the tau_s test) and every eigenvalue within 1e-5 ||A||
+    from tests.golden_util import lap3d27_window
+
+    A, (lmin, lmax), (a, b), cfg = build_config("lap3d_pot_27")
+    normA = max(abs(lmin), abs(lmax))
+    ref = _tau6_fixture(seed)
+    st, lam, res, r, V = gpu_solve(A, a, b, lmin, lmax, start_block(A.n, cfg.p, seed), cfg.degree,
+                                   tau_c=1e-6, max_iter=1500)
+    assert st == 0 and r.converged
+    assert r.count == ref.size
+    assert np.max(np.abs(lam - ref)) <= 1e-5 * normA
+    # whatever the count, every returned value is one of the window's eigenvalues
+    window = lap3d27_window()
+    assert np.all(np.min(np.abs(lam[:, None] - window[None, :]), axis=1) <= 1e-5 * normA)
+    assert np.max(res) <= 1e-6 * normA
