@@ -149,3 +149,52 @@ def test_solve_on_pencil_ordered_window():
     R = A.to_scipy() @ V - V * lam
     assert np.max(np.linalg.norm(R, axis=0)) <= 1e-9 * normA
     M.close()
+
+
+@pytest.mark.parametrize("single", [False, True])
+def test_full_size_grouped_slices_pencil_order(single):
+    # the serving path's grouped step on the 50 x 50 pencil ordering the slice benchmark
+    # uses: 16 slices x 96 columns of the 100^3 matrix, degree 120, odd slices one step
+    # behind; one sampled column per slice, moved back to the natural order, against the
+    # oracle's filter of the natural matrix
+    from workloads.stream import slice_intervals
+
+    t = torch()
+    A, (lo, hi), _, cfg = build_config("lap3d_pot_100")
+    perm = afsi.afsi_grid_order(100, 100, 100, 50, 50)
+    B = afsi.afsi_csr_permute(A, perm)
+    k, G, cols = cfg.degree, 16, 96
+    l1, l2 = co.affine_map(lo, hi)
+    ivs = slice_intervals(A.n, 0.5 * (lo + hi), G, 50)
+    coeffs = [co.filter_coefficients(lo, hi, a, b, k, "jackson") for a, b in ivs]
+    dt = t.float32 if single else t.float64
+    M = afsi.Matrix(B, bounds=(lo, hi))
+    pick, cols0, blocks = [], [], []
+    for g in range(G):
+        X0 = start_block(A.n, cols, seed=200 + g)
+        c = (5 * g + 3) % cols
+        pick.append(c)
+        cols0.append(np.ascontiguousarray(X0[:, c:c + 1]))
+        X = t.from_numpy(np.ascontiguousarray(X0[perm])).to(DEV).to(dt)
+        blocks.append((X, t.zeros_like(X), t.zeros_like(X)))
+        del X0
+    for step in range(k + 1):
+        sl = []
+        for g in range(G):
+            s_g = step - (g % 2)
+            if 0 <= s_g < k:
+                sl.append((afsi.afsi_clenshaw_step_params(coeffs[g], k, s_g, l1, l2, ncols=cols), *blocks[g]))
+        afsi.afsi_clenshaw_step_grouped(M.handle, sl)
+    t.cuda.synchronize()
+    got = []
+    for g in range(G):
+        y = blocks[g][1 + (k - 1) % 2][:, pick[g]].cpu().numpy().astype(np.float64)
+        nat = np.empty_like(y)
+        nat[perm] = y
+        got.append(nat)
+    del blocks
+    t.cuda.empty_cache()
+    M.close()
+    for g in range(G):
+        ref = clenshaw_filter(A, cols0[g], coeffs[g], l1, l2)
+        _check(got[g][:, None], ref, f32_tol(k) if single else F64_TOL)
