@@ -355,6 +355,21 @@ int afsi_rayleigh_ritz(afsi_matrix_t A, const afsi_block *Q, afsi_block *V, afsi
                        double *ritz_out, void *stream);
 
 /*
+ * One iteration's orthonormalisation and Rayleigh-Ritz (Algorithm 4's orthogonalisation
+ * step without locked vectors, then Algorithm 1's Rayleigh-Ritz) with the orthonormal
+ * basis left implicit: CholQR2 as afsi_orthonormalize up to its last factor R, where
+ * Q = Y R^-1 for the last pass's input Y; then B = R^-H (Y^H A Y) R^-1 (= Q^H A Q),
+ * B = U diag(ritz) U^H, V = Y (R^-1 U) (= Q U) and AV = A V, as afsi_rayleigh_ritz.
+ * This saves the n x p x p product that forms Q.  X (consumed: holds Y or a scratch
+ * state on return), work, V, AV: n x p, R64 or C128, one leading dimension; V must not
+ * overlap X or work; AV may be `work` (not X or V); ritz_out[p] (host) ascending.
+ * Errors as afsi_orthonormalize and afsi_rayleigh_ritz.  Synchronises `stream`.
+ */
+int afsi_orthonormalize_rayleigh_ritz(afsi_matrix_t A, afsi_block *X, afsi_block *work,
+                                      afsi_block *V, afsi_block *AV, double *ritz_out,
+                                      void *stream);
+
+/*
  * norms_out[j] = || AV[:, j] - lambda[j] V[:, j] ||_2 for j < V.cols (host output,
  * Algorithm 4 residual step).  R64 or C128.  Synchronises `stream`.
  */

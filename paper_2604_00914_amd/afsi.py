@@ -122,6 +122,7 @@ _SIGS = {
     "afsi_block_gemm": (C.c_int, [_BP, _BP, C.c_double, _BP, _P]),
     "afsi_orthonormalize": (C.c_int, [_BP, _BP, _BP, _P]),
     "afsi_rayleigh_ritz": (C.c_int, [_P, _BP, _BP, _BP, _P, _P]),
+    "afsi_orthonormalize_rayleigh_ritz": (C.c_int, [_P, _BP, _BP, _BP, _BP, _P, _P]),
     "afsi_residual_norms": (C.c_int, [_BP, _BP, _P, _P, _P]),
     "afsi_residual_norms_noalloc": (C.c_int, [_BP, _BP, _P, _P, _P]),
     "afsi_convert_block": (C.c_int, [_BP, _BP, _P]),
@@ -387,6 +388,14 @@ def afsi_rayleigh_ritz(h, Q, V, AV, stream=None) -> np.ndarray:
     q = _blk(Q)
     ritz = np.empty(q.cols, dtype=np.float64)
     _check(lib().afsi_rayleigh_ritz(h, _bref(q), _bref(_blk(V)), _bref(_blk(AV)), _ptr(ritz), _stream(stream)))
+    return ritz
+
+
+def afsi_orthonormalize_rayleigh_ritz(h, X, work, V, AV, stream=None) -> np.ndarray:
+    x = _blk(X)
+    ritz = np.empty(x.cols, dtype=np.float64)
+    _check(lib().afsi_orthonormalize_rayleigh_ritz(h, _bref(x), _bref(_blk(work)), _bref(_blk(V)),
+                                                   _bref(_blk(AV)), _ptr(ritz), _stream(stream)))
     return ritz
 
 

@@ -3,6 +3,7 @@
 // (clenshaw_*.hip, dense.hip, util.hip); small p x p factorisations run on the host
 // (host_linalg.cpp).
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
@@ -307,11 +308,13 @@ void project_out_dev(int dtype, const void *L, int64_t ldl, int64_t k, void *X, 
     }
 }
 
-// CholQR2 with shifted CholQR3 fallback.  X and W: n x p, same ld.  Result in X.
+// CholQR2 with shifted CholQR3 fallback.  X and W: n x p, same ld.
 // max_col_norm2 (optional): largest squared column norm of X on entry.
-void orthonormalize_dev(int dtype, void *X, void *W, int64_t n, int64_t p, int64_t ld,
-                        hipStream_t s, double *max_col_norm2) {
-    if (p == 0) return;
+// Without rinv the result is in X (returned).  With rinv (host, comp p^2 doubles) the
+// last pass's product is not formed: Q = Y R^{-1} with Y the returned block (X or W)
+// and R^{-1} (upper triangular, row-major) in rinv.
+static void *cholqr_passes(int dtype, void *X, void *W, int64_t n, int64_t p, int64_t ld,
+                           hipStream_t s, double *max_col_norm2, double *rinv) {
     const bool cplx = dtype == AFSI_C128;
     const int comp = cplx ? 2 : 1;
     const size_t gbytes = sizeof(double) * comp * p * p;
@@ -332,7 +335,10 @@ void orthonormalize_dev(int dtype, void *X, void *W, int64_t n, int64_t p, int64
         }
         // host_cholesky_inverse leaves Gh untouched when it reports a breakdown
         if (host_cholesky_inverse(p, cplx, Gh, p, 0.0)) {
-            ++plain_passes;
+            if (++plain_passes == 2 && rinv) {
+                std::memcpy(rinv, Gh, gbytes);
+                return cur;
+            }
         } else {
             // shifted Cholesky QR (Fukaya et al. 2020): s = 11 (n p + p (p+1)) u ||X||_F^2,
             // followed by two plain passes
@@ -353,6 +359,50 @@ void orthonormalize_dev(int dtype, void *X, void *W, int64_t n, int64_t p, int64
         const int eb = elem_bytes(dtype);
         AFSI_HIP(hipMemcpy2DAsync(X, ld * eb, cur, ld * eb, p * eb, n, hipMemcpyDeviceToDevice, s));
     }
+    AFSI_HIP(hipStreamSynchronize(s));
+    return X;
+}
+
+void orthonormalize_dev(int dtype, void *X, void *W, int64_t n, int64_t p, int64_t ld,
+                        hipStream_t s, double *max_col_norm2) {
+    if (p == 0) return;
+    cholqr_passes(dtype, X, W, n, p, ld, s, max_col_norm2, nullptr);
+}
+
+// CholQR2 of X fused with Rayleigh-Ritz on its basis Q, which is never formed: with the
+// last pass's input Y and factor R, Q = Y R^{-1}, so Q^H A Q = R^{-H} (Y^H A Y) R^{-1} and
+// V = Q U = Y (R^{-1} U): one n x p x p block product fewer than orthonormalising first.
+// The p x p products run on the device: T = (Y^H A Y) R^{-1}, then T^H R^{-1} (equal to
+// R^{-H} (Y^H A Y) R^{-1} since Y^H A Y is Hermitian), and R^{-1} U.  V must differ from
+// X and W; AV may be W.  orth_ms (optional): host time until the Cholesky-QR part is done.
+void orthonormalize_rr_dev(afsi_matrix_t A, int dtype, void *X, void *W, void *V, void *AV,
+                           int64_t n, int64_t p, int64_t ld, double *ritz, hipStream_t s,
+                           double *max_col_norm2, double *orth_ms) {
+    if (p == 0) return;
+    const auto t0 = std::chrono::steady_clock::now();
+    const bool cplx = dtype == AFSI_C128;
+    const int comp = cplx ? 2 : 1;
+    const size_t mel = (size_t)comp * p * p, mbytes = sizeof(double) * mel;
+    std::vector<double> rinv(mel), U(mel);
+    void *Y = cholqr_passes(dtype, X, W, n, p, ld, s, max_col_norm2, rinv.data());
+    if (orth_ms)
+        *orth_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    Workspace &ws = workspace(s);
+    double *Bd = (double *)ws.dev_reserve(SLOT_SMALL, 3 * mbytes);
+    double *Rd = Bd + mel, *Td = Rd + mel;
+    double *Hh = (double *)ws.host_reserve(0, mbytes);
+    AFSI_HIP(hipMemcpyAsync(Rd, rinv.data(), mbytes, hipMemcpyHostToDevice, s));
+    spmm_apply(A, dtype, Y, V, p, ld, s);                               // V <- A Y
+    inner_dev(dtype, Y, ld, V, ld, n, p, p, Bd, p, s);                  // Y^H A Y
+    gemm_dev(dtype, Bd, p, Rd, p, p, p, p, 1.0, 0.0, Td, p, s, true);   // T = (Y^H A Y) R^{-1}
+    inner_dev(dtype, Td, p, Rd, p, p, p, p, Bd, p, s);                  // Q^H A Q = T^H R^{-1}
+    AFSI_HIP(hipMemcpyAsync(Hh, Bd, mbytes, hipMemcpyDeviceToHost, s));
+    AFSI_HIP(hipStreamSynchronize(s));
+    host_eigh_or_throw(p, cplx, Hh, p, ritz, U.data(), p);
+    AFSI_HIP(hipMemcpyAsync(Td, U.data(), mbytes, hipMemcpyHostToDevice, s));
+    gemm_dev(dtype, Rd, p, Td, p, p, p, p, 1.0, 0.0, Bd, p, s);         // R^{-1} U
+    gemm_dev(dtype, Y, ld, Bd, p, n, p, p, 1.0, 0.0, V, ld, s);         // V  <- Q U
+    spmm_apply(A, dtype, V, AV, p, ld, s);                              // AV <- A V
     AFSI_HIP(hipStreamSynchronize(s));
 }
 
@@ -1011,6 +1061,32 @@ int afsi_rayleigh_ritz(afsi_matrix_t A, const afsi_block *Q, afsi_block *V, afsi
         DeviceGuard dg(A->device);
         rayleigh_ritz_dev(A, Q->dtype, Q->ptr, V->ptr, AV->ptr, Q->rows, Q->cols, Q->ld, ritz_out,
                           as_stream(stream));
+    });
+}
+
+int afsi_orthonormalize_rayleigh_ritz(afsi_matrix_t A, afsi_block *X, afsi_block *work,
+                                      afsi_block *V, afsi_block *AV, double *ritz_out,
+                                      void *stream) {
+    return guarded([&] {
+        check_matrix(A);
+        check_block(X, "X");
+        check_block(work, "work");
+        check_block(V, "V");
+        check_block(AV, "AV");
+        check_fp64(X, "X");
+        check_same_shape(X, work, "X", "work");
+        check_same_shape(X, V, "X", "V");
+        check_same_shape(X, AV, "X", "AV");
+        AFSI_REQUIRE(X->rows == A->n, "X rows != n");
+        AFSI_REQUIRE(X->ld == work->ld && X->ld == V->ld && X->ld == AV->ld,
+                     "X, work, V and AV must share one leading dimension");
+        AFSI_REQUIRE(!overlap(X, work) && !overlap(X, V) && !overlap(work, V) && !overlap(X, AV) &&
+                         !overlap(V, AV),
+                     "blocks overlap (only AV and work may share memory)");
+        AFSI_REQUIRE(ritz_out != nullptr || X->cols == 0, "ritz_out is NULL");
+        DeviceGuard dg(A->device);
+        orthonormalize_rr_dev(A, X->dtype, X->ptr, work->ptr, V->ptr, AV->ptr, X->rows, X->cols,
+                              X->ld, ritz_out, as_stream(stream), nullptr, nullptr);
     });
 }
 

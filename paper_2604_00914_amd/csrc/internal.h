@@ -267,6 +267,11 @@ void orthonormalize_dev(int dtype, void *X, void *W, int64_t n, int64_t p, int64
                         hipStream_t s, double *max_col_norm2);
 void rayleigh_ritz_dev(afsi_matrix_t A, int dtype, const void *Q, void *V, void *AV, int64_t n,
                        int64_t p, int64_t ld, double *ritz, hipStream_t s);
+// CholQR2 of X (work W) fused with Rayleigh-Ritz on the basis it defines, which is never
+// formed; V and AV as rayleigh_ritz_dev.  V must differ from X and W; AV may be W.
+void orthonormalize_rr_dev(afsi_matrix_t A, int dtype, void *X, void *W, void *V, void *AV,
+                           int64_t n, int64_t p, int64_t ld, double *ritz, hipStream_t s,
+                           double *max_col_norm2, double *orth_ms);
 void residual_norms_host(int dtype, const void *V, int64_t ldv, const void *AV, int64_t ldav,
                          const double *lambda, int64_t n, int64_t q, double *out, hipStream_t s);
 void lock_select(const double *ritz, int64_t p, const double *res, uint8_t *I, double a, double b,

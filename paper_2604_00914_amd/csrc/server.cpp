@@ -429,12 +429,11 @@ int dense_phase(Pool *P, Session &s, hipStream_t st) {
     publish(P, r, 1, (int64_t)s.k_cur * pa, 0);
     if (r->n_lock > 0) project_out_dev(dt, r->evecs, r->p, r->n_lock, q, ld, n, pa, st);
     double maxn2 = 0.0;
-    orthonormalize_dev(dt, q, w, n, pa, ld, st, &maxn2);
+    std::vector<double> ritz(pa), res(pa);
+    orthonormalize_rr_dev(r->A, dt, q, w, v, w, n, pa, ld, ritz.data(), st, &maxn2, nullptr);
     if (r->opts.damping != AFSI_DAMP_NONE && maxn2 > 16.0)
         AFSI_FAIL(AFSI_E_BOUNDS, "filtered block grew by %.3g: spectral bounds do not enclose A",
                   std::sqrt(maxn2));
-    std::vector<double> ritz(pa), res(pa);
-    rayleigh_ritz_dev(r->A, dt, q, v, w, n, pa, ld, ritz.data(), st);
     publish(P, r, 0, pa, 0);
     std::vector<uint8_t> I(pa), lock(pa);
     int64_t e = 0;

@@ -108,6 +108,48 @@ def test_rayleigh_ritz_matches_oracle(name):
     M.close()
 
 
+@pytest.mark.parametrize("graded", [False, True])
+@pytest.mark.parametrize("name", ["lap2d_64", "tb3d_64"])
+def test_orthonormalize_rayleigh_ritz_matches_oracle(name, graded):
+    # the fused call (the basis Q of Cholesky QR left implicit) against the oracle's
+    # Householder QR followed by its Rayleigh-Ritz, on a raw (not orthonormal) block;
+    # graded columns (norms 1 .. 1e-6) make the first Cholesky pass visibly inexact
+    t = torch()
+    size = 64 if name == "lap2d_64" else 10
+    A, (lmin, lmax), _, cfg = build_config(name, size=size)
+    cplx = A.is_complex
+    p = 40
+    X0 = _rand(A.n, p, cplx, 11)
+    if graded:
+        X0 = X0 * np.logspace(0, -6, p)[None, :]
+    normA = max(abs(lmin), abs(lmax))
+    w, Vo, AVo = odense.rayleigh_ritz(A, odense.orthonormalize(X0))
+    M = afsi.Matrix(A, bounds=(lmin, lmax))
+    X = to_dev(X0)
+    W, V = t.empty_like(X), t.empty_like(X)
+    ritz = afsi.afsi_orthonormalize_rayleigh_ritz(M.handle, X, W, V, W)   # AV in the work block
+    assert np.max(np.abs(ritz - w)) < 1e-12 * normA
+    Vg, AVg = V.cpu().numpy(), W.cpu().numpy()
+    assert np.max(np.abs(Vg.conj().T @ Vg - np.eye(p))) < 1e-12
+    assert np.max(np.abs(A.to_scipy() @ Vg - AVg)) < 1e-12 * normA
+    # same Ritz vectors (up to a unit factor) where the Ritz values are apart
+    gap = np.minimum(np.r_[np.inf, np.diff(w)], np.r_[np.diff(w), np.inf])
+    sep = gap > 1e-6 * normA
+    assert np.all(np.abs(np.abs(np.sum(Vo.conj() * Vg, axis=0))[sep] - 1) < 1e-8)
+    M.close()
+
+
+def test_orthonormalize_rayleigh_ritz_rejects_overlap():
+    t = torch()
+    A, (lmin, lmax), _, cfg = build_config("lap2d_64", size=16)
+    M = afsi.Matrix(A, bounds=(lmin, lmax))
+    X = to_dev(_rand(A.n, 8, False, 1))
+    W = t.empty_like(X)
+    with pytest.raises(afsi.AfsiError):
+        afsi.afsi_orthonormalize_rayleigh_ritz(M.handle, X, W, W, X)   # V on the work block
+    M.close()
+
+
 def test_convert_and_gather():
     t = torch()
     X0 = _rand(777, 13, True, 10)
