@@ -396,6 +396,7 @@ def main():
         out["lanczos"] = lanczos_rates(afsi, torch, dev)
         out["eigencount"] = eigencount_rates(afsi, torch, dev)
         out["irregular"] = irregular_record(afsi, torch, dev)
+        out["complex"] = complex_record(afsi, torch, dev)
     if not args.no_serve:
         out["serve"] = serve_rates(afsi, M, args.serve_requests)
 
@@ -945,6 +946,36 @@ def irregular_record(afsi, torch, dev, products=8):
     M.close()
     del X, Y, W
     torch.cuda.empty_cache()
+    return rec
+
+
+def complex_record(afsi, torch, dev, products=8):
+    """The complex lattice (64^3 periodic tight binding, n = 262144, 7 complex entries per
+    row) at its block width p = 192: steady Clenshaw products in complex FP64 (C128) and
+    complex FP32 (C64), HIP events, against the compulsory bytes (A once + four passes of
+    the block).  The block is N(0,1) + i N(0,1) drawn on the device."""
+    from workloads import build_config
+
+    A, (lmin, lmax), (a, b), cfg = build_config("tb3d_64")
+    M = afsi.Matrix(A, device=0, bounds=(lmin, lmax))
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(0)
+    coeffs = afsi.afsi_filter_coefficients(lmin, lmax, a, b, products, cfg.damping)
+    rec = {"n": A.n, "nnz": A.nnz, "p": cfg.p}
+    for name, dt, sx in (("c128", torch.complex128, 16), ("c64", torch.complex64, 8)):
+        X = torch.randn((A.n, cfg.p), dtype=dt, device=dev, generator=gen)
+        Y, W = torch.empty_like(X), torch.empty_like(X)
+        afsi.afsi_filter_block_profiled(M.handle, coeffs, products, X, Y, W)  # warm-up
+        ms, kind = afsi.afsi_filter_block_profiled(M.handle, coeffs, products, X, Y, W)
+        steady = float(np.mean(ms[2:][kind[2:] == 3]))
+        comp = A.nnz * (sx + 4) + 4 * (A.n + 1) + 4 * A.n * cfg.p * sx
+        rec[name] = {"steady_product_us": round(steady * 1e3, 1), "compulsory_bytes": comp,
+                     "gbs": round(comp / (steady * 1e-3) / 1e9, 1),
+                     "frac": round(comp / (steady * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        del X, Y, W
+        torch.cuda.empty_cache()
+    log(f"complex tb3d_64: {rec}")
+    M.close()
     return rec
 
 
