@@ -953,11 +953,15 @@ def complex_record(afsi, torch, dev, products=8):
     """The complex lattice (64^3 periodic tight binding, n = 262144, 7 complex entries per
     row) at its block width p = 192: steady Clenshaw products in complex FP64 (C128) and
     complex FP32 (C64), HIP events, against the compulsory bytes (A once + four passes of
-    the block).  The block is N(0,1) + i N(0,1) drawn on the device."""
+    the block); in folded 16 x 16 pencils (afsi_grid_order with fold_x: the periodic x
+    neighbours at most two cross-sections apart) and, for comparison, the natural order.
+    The block is N(0,1) + i N(0,1) drawn on the device."""
     from workloads import build_config
 
     A, (lmin, lmax), (a, b), cfg = build_config("tb3d_64")
-    M = afsi.Matrix(A, device=0, bounds=(lmin, lmax))
+    L = cfg.size
+    orders = {"folded_pencil_16x16": afsi.afsi_csr_permute(A, afsi.afsi_grid_order(L, L, L, 16, 16, fold_x=True)),
+              "natural": A}
     gen = torch.Generator(device=dev)
     gen.manual_seed(0)
     coeffs = afsi.afsi_filter_coefficients(lmin, lmax, a, b, products, cfg.damping)
@@ -965,17 +969,25 @@ def complex_record(afsi, torch, dev, products=8):
     for name, dt, sx in (("c128", torch.complex128, 16), ("c64", torch.complex64, 8)):
         X = torch.randn((A.n, cfg.p), dtype=dt, device=dev, generator=gen)
         Y, W = torch.empty_like(X), torch.empty_like(X)
-        afsi.afsi_filter_block_profiled(M.handle, coeffs, products, X, Y, W)  # warm-up
-        ms, kind = afsi.afsi_filter_block_profiled(M.handle, coeffs, products, X, Y, W)
-        steady = float(np.mean(ms[2:][kind[2:] == 3]))
         comp = A.nnz * (sx + 4) + 4 * (A.n + 1) + 4 * A.n * cfg.p * sx
-        rec[name] = {"steady_product_us": round(steady * 1e3, 1), "compulsory_bytes": comp,
-                     "gbs": round(comp / (steady * 1e-3) / 1e9, 1),
-                     "frac": round(comp / (steady * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        rec[name] = {"compulsory_bytes": comp}
+        for oname, B in orders.items():
+            M = afsi.Matrix(B, device=0, bounds=(lmin, lmax))
+            afsi.afsi_filter_block_profiled(M.handle, coeffs, products, X, Y, W)  # warm-up
+            ms, kind = afsi.afsi_filter_block_profiled(M.handle, coeffs, products, X, Y, W)
+            M.close()
+            steady = float(np.mean(ms[2:][kind[2:] == 3]))
+            gbs = comp / (steady * 1e-3) / 1e9
+            r = {"steady_product_us": round(steady * 1e3, 1), "gbs": round(gbs, 1),
+                 "frac": round(gbs / HBM_PEAK_GBS, 4)}
+            if oname == "natural":
+                rec[name]["natural"] = r
+            else:
+                rec[name].update(r)
+                rec[name]["ordering"] = oname
         del X, Y, W
         torch.cuda.empty_cache()
     log(f"complex tb3d_64: {rec}")
-    M.close()
     return rec
 
 

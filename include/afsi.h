@@ -124,11 +124,14 @@ int afsi_matrix_get_column_block(afsi_matrix_t A, int64_t *bytes);
  * +-x neighbours of a point sit ty tz rows away, so for a 7-point stencil almost every
  * neighbour lies within a constant row distance (the tile's cross-section) instead of
  * ny nz rows; the products pick that distance up from the matrix and run each XCD on
- * rows that many positions apart, keeping the reused rows in its own L2.  Writes
- * perm[new] = old for all nx ny nz points (caller-allocated host array).
- * AFSI_E_INVALID for negative sizes or tiles smaller than 1.
+ * rows that many positions apart, keeping the reused rows in its own L2.  fold_x != 0
+ * (for a periodic x axis) takes x in the order 0, nx-1, 1, nx-2, ... along every pencil,
+ * so the wrap-around neighbours are adjacent and every +-x neighbour is at most two
+ * cross-sections away.  Writes perm[new] = old for all nx ny nz points (caller-allocated
+ * host array).  AFSI_E_INVALID for negative sizes or tiles smaller than 1.
  */
-int afsi_grid_order(int64_t nx, int64_t ny, int64_t nz, int64_t ty, int64_t tz, int64_t *perm);
+int afsi_grid_order(int64_t nx, int64_t ny, int64_t nz, int64_t ty, int64_t tz, int32_t fold_x,
+                    int64_t *perm);
 
 /*
  * B = P A P^T in CSR on the host: B[i][j] = A[perm[i]][perm[j]], i.e. row i of B is row

@@ -128,7 +128,7 @@ _SIGS = {
     "afsi_convert_block": (C.c_int, [_BP, _BP, _P]),
     "afsi_gather_columns": (C.c_int, [_BP, _P, C.c_int64, _BP, _P]),
     "afsi_permute_rows": (C.c_int, [_BP, _P, C.c_int32, _BP, _P]),
-    "afsi_grid_order": (C.c_int, [C.c_int64, C.c_int64, C.c_int64, C.c_int64, C.c_int64, _P]),
+    "afsi_grid_order": (C.c_int, [C.c_int64, C.c_int64, C.c_int64, C.c_int64, C.c_int64, C.c_int32, _P]),
     "afsi_csr_permute": (C.c_int, [C.c_int64, C.c_int64, _P, _P, _P, C.c_int32, _P, _P, _P, _P]),
     "afsi_select_degree": (C.c_int, [_P, C.c_int64, C.c_int64, _P, C.c_int, C.c_double, C.c_double, C.c_double, C.POINTER(C.c_int)]),
     "afsi_lock_select": (C.c_int, [_P, C.c_int64, _P, _P, C.c_double, C.c_double, C.c_double, C.c_int64, _I64P, _P, C.POINTER(C.c_int)]),
@@ -431,10 +431,10 @@ def afsi_permute_rows(src, perm, dst, inverse: bool = False, stream=None):
     _check(lib().afsi_permute_rows(_bref(_blk(src)), _ptr(pm), int(bool(inverse)), _bref(_blk(dst)), _stream(stream)))
 
 
-def afsi_grid_order(nx: int, ny: int, nz: int, ty: int, tz: int) -> np.ndarray:
-    """Pencil ordering of an nx x ny x nz grid (perm[new] = old)."""
+def afsi_grid_order(nx: int, ny: int, nz: int, ty: int, tz: int, fold_x: bool = False) -> np.ndarray:
+    """Pencil ordering of an nx x ny x nz grid (perm[new] = old); fold_x for a periodic x."""
     perm = np.empty(max(0, nx * ny * nz), dtype=np.int64)
-    _check(lib().afsi_grid_order(nx, ny, nz, ty, tz, _ptr(perm)))
+    _check(lib().afsi_grid_order(nx, ny, nz, ty, tz, int(bool(fold_x)), _ptr(perm)))
     return perm
 
 

@@ -1182,21 +1182,27 @@ int afsi_permute_rows(const afsi_block *src, const int64_t *perm, int32_t invers
     });
 }
 
-int afsi_grid_order(int64_t nx, int64_t ny, int64_t nz, int64_t ty, int64_t tz, int64_t *perm) {
+int afsi_grid_order(int64_t nx, int64_t ny, int64_t nz, int64_t ty, int64_t tz, int32_t fold_x,
+                    int64_t *perm) {
     return guarded([&] {
         AFSI_REQUIRE(nx >= 0 && ny >= 0 && nz >= 0, "negative grid size");
         AFSI_REQUIRE(ty >= 1 && tz >= 1, "tile sides must be at least 1");
         const int64_t n = nx * ny * nz;
         AFSI_REQUIRE(n == 0 || perm != nullptr, "perm is NULL");
+        // x positions along a pencil: natural, or folded (0, nx-1, 1, nx-2, ...) so that on a
+        // periodic x axis every neighbour, the wrap-around pair included, is at most two
+        // positions away
+        std::vector<int64_t> xs(nx);
+        for (int64_t i = 0; i < nx; ++i) xs[i] = !fold_x ? i : (i % 2 == 0 ? i / 2 : nx - 1 - i / 2);
         // pencils: ty x tz tiles of the (y, z) plane, one after another (y tile outer), each
         // running along x with its (y, z) points in natural order at every x
         int64_t k = 0;
         for (int64_t y0 = 0; y0 < ny; y0 += ty)
             for (int64_t z0 = 0; z0 < nz; z0 += tz)
-                for (int64_t x = 0; x < nx; ++x)
+                for (int64_t xi = 0; xi < nx; ++xi)
                     for (int64_t y = y0; y < std::min(ny, y0 + ty); ++y)
                         for (int64_t z = z0; z < std::min(nz, z0 + tz); ++z)
-                            perm[k++] = (x * ny + y) * nz + z;
+                            perm[k++] = (xs[xi] * ny + y) * nz + z;
     });
 }
 

@@ -104,6 +104,35 @@ def test_ordered_filter_matches_oracle(tiles):
         _check(got, ref, f32_tol(k) if single else F64_TOL)
 
 
+@pytest.mark.parametrize("single", [False, True])
+def test_folded_order_filter_on_periodic_lattice(single):
+    # the complex periodic lattice in folded pencils (C128 and C64): the filter of P A P^T
+    # on P X, moved back, against the oracle's filter of the natural matrix
+    from workloads import tight_binding_3d_periodic
+
+    t = torch()
+    L = 16
+    A = tight_binding_3d_periodic(L, seed=3)
+    lmin, lmax, a, b, k = -7.0, 7.0, -0.4, 0.3, 60
+    perm = afsi.afsi_grid_order(L, L, L, 8, 8, fold_x=True)
+    B = afsi.afsi_csr_permute(A, perm)
+    X0 = start_block(A.n, 32, seed=4, complex_=True)
+    c = co.filter_coefficients(lmin, lmax, a, b, k, "jackson")
+    l1, l2 = co.affine_map(lmin, lmax)
+    ref = clenshaw_filter(A, X0, c, l1, l2)
+    M = afsi.Matrix(B, bounds=(lmin, lmax))
+    dt = t.complex64 if single else t.complex128
+    Xn = t.from_numpy(X0).to(DEV).to(dt)
+    X = t.empty_like(Xn)
+    afsi.afsi_permute_rows(Xn, perm, X)
+    Y, W = t.empty_like(X), t.empty_like(X)
+    afsi.afsi_filter_block(M.handle, c, k, X, Y, W)
+    afsi.afsi_permute_rows(Y, perm, Xn, inverse=True)
+    got = Xn.cpu().numpy().astype(np.complex128)
+    M.close()
+    _check(got, ref, f32_tol(k) if single else F64_TOL)
+
+
 def test_full_size_pencil_order_sampled_columns():
     # the benchmark's launch configuration: lap3d_pot_100 in 25 x 25 pencils, n = 1e6,
     # p = 256, the workload's degree, FP64 and FP32; columns act independently, so

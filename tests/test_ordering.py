@@ -14,11 +14,14 @@ from paper_2604_00914_amd import afsi
 from workloads import laplacian_3d_dirichlet, random_banded_symmetric, tight_binding_3d_periodic
 
 
-def _loops(nx, ny, nz, ty, tz):
+def _loops(nx, ny, nz, ty, tz, fold=False):
+    xs = list(range(nx))
+    if fold:  # 0, nx-1, 1, nx-2, ...
+        xs = [xs[i // 2] if i % 2 == 0 else xs[nx - 1 - i // 2] for i in range(nx)]
     out = []
     for y0 in range(0, ny, ty):
         for z0 in range(0, nz, tz):
-            for x in range(nx):
+            for x in xs:
                 for y in range(y0, min(ny, y0 + ty)):
                     for z in range(z0, min(nz, z0 + tz)):
                         out.append((x * ny + y) * nz + z)
@@ -32,6 +35,27 @@ def test_grid_order_is_the_tiled_loop_order(dims):
     assert np.array_equal(perm, _loops(*dims))
     n = dims[0] * dims[1] * dims[2]
     assert np.array_equal(np.sort(perm), np.arange(n))
+
+
+@pytest.mark.parametrize("dims", [(5, 7, 6, 3, 4), (6, 4, 4, 4, 4), (1, 2, 2, 1, 1), (9, 3, 11, 2, 5)])
+def test_grid_order_folded_is_the_tiled_loop_order(dims):
+    perm = afsi.afsi_grid_order(*dims, fold_x=True)
+    assert np.array_equal(perm, _loops(*dims, fold=True))
+
+
+def test_folded_order_keeps_periodic_neighbours_close():
+    # the periodic 16^3 lattice in folded 4 x 8 pencils: every +-x neighbour (the
+    # wrap-around pair included) is at most two cross-sections (2 * 32 rows) away
+    L, ty, tz = 16, 4, 8
+    A = tight_binding_3d_periodic(L, seed=0)
+    perm = afsi.afsi_grid_order(L, L, L, ty, tz, fold_x=True)
+    pos = np.empty_like(perm)
+    pos[perm] = np.arange(perm.size)
+    rows = np.repeat(np.arange(A.n), np.diff(A.row_ptr))
+    cols = A.col.astype(np.int64)
+    xr, xc = rows // (L * L), cols // (L * L)
+    xnb = xr != xc
+    assert np.all(np.abs(pos[rows[xnb]] - pos[cols[xnb]]) <= 2 * ty * tz)
 
 
 def test_grid_order_neighbour_distance():
