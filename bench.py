@@ -398,7 +398,17 @@ def main():
         out["irregular"] = irregular_record(afsi, torch, dev)
         out["complex"] = complex_record(afsi, torch, dev)
     if not args.no_serve:
-        out["serve"] = serve_rates(afsi, M, args.serve_requests)
+        # the slices of the serving stream run on the matrix in the pencil ordering for
+        # 96-column rows (SLICE_PENCIL), as in the slice-step record
+        Ms = M
+        if perm is not None:
+            Ms = afsi.Matrix(afsi.afsi_csr_permute(A, afsi.afsi_grid_order(gsize, gsize, gsize, SLICE_PENCIL,
+                                                                           SLICE_PENCIL)),
+                             device=0, bounds=(lmin, lmax))
+        out["serve"] = serve_rates(afsi, Ms, args.serve_requests)
+        out["serve"]["slice_ordering"] = f"pencil {SLICE_PENCIL}x{SLICE_PENCIL}" if perm is not None else "natural"
+        if Ms is not M:
+            Ms.close()
 
     out["paper_context"] = paper_context()
     # the same rate for this GPU's steady product (nonzeros x block columns per second)
