@@ -79,7 +79,7 @@ def filter_bytes(nnz, n, p, sx, sval, coeffs, degree):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--form", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--workload", default="lap3d_pot_100")
