@@ -459,6 +459,7 @@ static bool dc_eig(int64_t n, double *d, double *e, double *Z, int64_t ldz) {
     const double tol = 8.0 * eps * std::max(dmax, rho);
     // columns of diag(Q1, Q2) in pole order; deflating rotations act on them
     std::vector<double> Q((size_t)n * n);
+#pragma omp parallel for schedule(static) if (n >= 128)
     for (int64_t i = 0; i < n; ++i)
         for (int64_t j = 0; j < n; ++j) Q[(size_t)i * n + j] = Z[i * ldz + perm[j]];
     std::vector<char> defl(n, 0);
@@ -530,6 +531,7 @@ static bool dc_eig(int64_t n, double *d, double *e, double *Z, int64_t ldz) {
     }
     // new eigenvectors: Q_k U for the roots, the deflated columns as they are
     std::vector<double> Qk((size_t)n * k), QU((size_t)n * k);
+#pragma omp parallel for schedule(static) if (n >= 128)
     for (int64_t row = 0; row < n; ++row)
         for (int64_t t = 0; t < k; ++t) Qk[(size_t)row * k + t] = Q[(size_t)row * n + keep[t]];
     dense_product(n, k, Qk.data(), k, U.data(), k, QU.data(), k);
@@ -543,11 +545,17 @@ static bool dc_eig(int64_t n, double *d, double *e, double *Z, int64_t ldz) {
                      [](const std::pair<double, int64_t> &x, const std::pair<double, int64_t> &y) {
                          return x.first < y.first;
                      });
-    for (int64_t j = 0; j < n; ++j) {
-        d[j] = all[j].first;
-        const int64_t src = all[j].second;
-        for (int64_t row = 0; row < n; ++row)
-            Z[row * ldz + j] = src >= 0 ? QU[(size_t)row * k + src] : Q[(size_t)row * n + (-src - 1)];
+    // row by row (Z is row-major): column j of Z is root all[j].second's column of QU, or
+    // a deflated column of Q
+    for (int64_t j = 0; j < n; ++j) d[j] = all[j].first;
+#pragma omp parallel for schedule(static) if (n >= 128)
+    for (int64_t row = 0; row < n; ++row) {
+        const double *qu = &QU[(size_t)row * k], *q = &Q[(size_t)row * n];
+        double *z = Z + row * ldz;
+        for (int64_t j = 0; j < n; ++j) {
+            const int64_t src = all[j].second;
+            z[j] = src >= 0 ? qu[src] : q[-src - 1];
+        }
     }
     return true;
 }
