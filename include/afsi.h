@@ -430,10 +430,11 @@ int afsi_lock_select(const double *ritz, int64_t p, const double *res, uint8_t *
  * Host Hermitian eigensolver used by Rayleigh-Ritz (Algorithm 1): B (p x p,
  * row-major, ldb; R64 or C128, only its Hermitian part is used) = U diag(w) U^H,
  * w[p] ascending, U (p x p, ldu, same dtype) unitary.  Householder tridiagonal
- * reduction + implicit-shift symmetric QR.  Pure host function.  AFSI_E_INVALID
- * if B has a non-finite entry; AFSI_E_NOCONV if the QR iteration does not converge
- * (also returned by afsi_rayleigh_ritz and afsi_solve; afsi_solve then reports no
- * locked pairs).
+ * reduction, then divide and conquer on the tridiagonal above 32 rows (implicit-shift
+ * symmetric QR for smaller blocks and as the fallback when a secular equation does not
+ * settle).  Pure host function.  AFSI_E_INVALID if B has a non-finite entry;
+ * AFSI_E_NOCONV if the QR iteration does not converge (also returned by
+ * afsi_rayleigh_ritz and afsi_solve; afsi_solve then reports no locked pairs).
  */
 int afsi_host_eigh(int64_t p, int32_t dtype, const double *B, int64_t ldb, double *w, double *U,
                    int64_t ldu);

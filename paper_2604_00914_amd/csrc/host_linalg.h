@@ -12,7 +12,7 @@ namespace afsi {
 bool host_cholesky_inverse(int64_t p, bool cplx, double *G, int64_t ld, double shift);
 
 // B (p x p Hermitian, row-major, ldb) = U diag(w) U^H with w ascending and U unitary
-// (row-major, ldu).  Returns false if the tridiagonal QR iteration does not converge.
+// (row-major, ldu).  Returns false if the tridiagonal eigensolver does not converge.
 bool host_eigh(int64_t p, bool cplx, const double *B, int64_t ldb, double *w, double *U,
                int64_t ldu);
 
