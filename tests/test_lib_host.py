@@ -187,6 +187,20 @@ def test_host_eigh_structured_spectra(cplx, p):
         assert np.max(np.abs(B @ U - U * w)) <= 1e-13 * max(scale, 1.0) * max(1, p / 32), name
 
 
+@pytest.mark.parametrize("p", [40, 97, 256])
+def test_host_eigh_closed_form_tridiagonal(p):
+    # the 1D Dirichlet Laplacian tridiag(-1, 2, -1): eigenvalues 2 - 2 cos(j pi / (p+1)),
+    # eigenvectors sin(i j pi / (p+1)) (distinct eigenvalues: unique up to sign); the
+    # input is already tridiagonal, so this pins the divide and conquer step directly
+    T = 2 * np.eye(p) - np.eye(p, k=1) - np.eye(p, k=-1)
+    w, U = afsi.afsi_host_eigh(T)
+    j = np.arange(1, p + 1)
+    lam = 2 - 2 * np.cos(j * np.pi / (p + 1))
+    V = np.sin(np.outer(j, j) * np.pi / (p + 1)) * np.sqrt(2 / (p + 1))
+    assert np.max(np.abs(w - lam)) < 1e-14 * max(1, p / 32)
+    assert np.max(np.abs(np.abs(np.sum(U * V, axis=0)) - 1)) < 1e-12
+
+
 @pytest.mark.parametrize("cplx", [False, True])
 def test_host_eigh_rejects_non_finite_input(cplx):
     B = np.eye(6, dtype=np.complex128 if cplx else np.float64)
