@@ -952,6 +952,20 @@ def irregular_record(afsi, torch, dev, products=8):
            "far_entries": far, "gather_inclusive_bytes": gathered,
            "gather_inclusive_gbs": round(gathered / (steady * 1e-3) / 1e9, 1)}
     rec["compulsory_frac"] = round(rec["compulsory_gbs"] / HBM_PEAK_GBS, 4)
+    # the same products in 256-byte column blocks of the dense operand (MaSpMM's loop over
+    # column blocks, afsi_matrix_set_column_block): A is read once per block, each block's
+    # gathered rows are reused from the memory-side cache while every row of A passes
+    afsi.afsi_matrix_set_column_block(M.handle, 256)
+    afsi.afsi_filter_block_profiled(M.handle, coeffs, products, X, Y, W)  # warm-up
+    ms, kind = afsi.afsi_filter_block_profiled(M.handle, coeffs, products, X, Y, W)
+    afsi.afsi_matrix_set_column_block(M.handle, 0)
+    blk = float(np.mean(ms[2:][kind[2:] == 3]))
+    blocks = -(-cfg.p * 4 // 256)
+    comp_blk = compulsory + (blocks - 1) * a_bytes
+    rec["column_blocks_256B"] = {"steady_product_us": round(blk * 1e3, 1),
+                                 "compulsory_bytes": comp_blk,
+                                 "compulsory_gbs": round(comp_blk / (blk * 1e-3) / 1e9, 1),
+                                 "speedup_vs_whole_rows": round(steady / blk, 3)}
     log(f"irregular rand_2m fp32: {rec}")
     M.close()
     del X, Y, W
