@@ -21,6 +21,7 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <type_traits>
 #include <cstdlib>
 #include <new>
 #include <limits>
@@ -611,6 +612,57 @@ static std::vector<ReflBlock<T>> reflector_blocks(int64_t p, const std::vector<s
     return out;
 }
 
+// Register-tiled forms of the two block-reflector products of the back-transformation
+// for real data, a chunk of kChunk columns and a block of a multiple of 4 reflectors.
+// Each output element accumulates its terms in the same order as the plain loops (over
+// rows r for W, over reflectors l for C), so the results are the same bits.
+//   W (cnt x kChunk) = V^T C, V: rows x cnt (row-major), C: rows x kChunk (ld ldc)
+static void refl_w_tiled(int64_t rows, int64_t cnt, const double *V, const double *C0, int64_t ldc,
+                         double *W) {
+    for (int64_t lb = 0; lb < cnt; lb += 4)
+        for (int64_t jb = 0; jb < kChunk; jb += 8) {
+            double acc[4][8] = {};
+            for (int64_t r = 0; r < rows; ++r) {
+                const double *cr = C0 + r * ldc + jb;
+                const double *vr = V + r * cnt + lb;
+                for (int a = 0; a < 4; ++a) {
+                    const double f = vr[a];
+                    for (int j = 0; j < 8; ++j) acc[a][j] += f * cr[j];
+                }
+            }
+            for (int a = 0; a < 4; ++a)
+                for (int j = 0; j < 8; ++j) W[(lb + a) * kChunk + jb + j] = acc[a][j];
+        }
+}
+//   C -= V W2, W2: cnt x kChunk
+static void refl_update_tiled(int64_t rows, int64_t cnt, const double *V, const double *W2,
+                              double *C0, int64_t ldc) {
+    int64_t r = 0;
+    for (; r + 4 <= rows; r += 4)
+        for (int64_t jb = 0; jb < kChunk; jb += 8) {
+            double acc[4][8];
+            for (int a = 0; a < 4; ++a)
+                for (int j = 0; j < 8; ++j) acc[a][j] = C0[(r + a) * ldc + jb + j];
+            for (int64_t l = 0; l < cnt; ++l) {
+                const double *w2 = W2 + l * kChunk + jb;
+                for (int a = 0; a < 4; ++a) {
+                    const double f = V[(r + a) * cnt + l];
+                    for (int j = 0; j < 8; ++j) acc[a][j] -= f * w2[j];
+                }
+            }
+            for (int a = 0; a < 4; ++a)
+                for (int j = 0; j < 8; ++j) C0[(r + a) * ldc + jb + j] = acc[a][j];
+        }
+    for (; r < rows; ++r) {
+        double *cr = C0 + r * ldc;
+        for (int64_t l = 0; l < cnt; ++l) {
+            const double f = V[r * cnt + l];
+            const double *w2 = W2 + l * kChunk;
+            for (int64_t j = 0; j < kChunk; ++j) cr[j] -= f * w2[j];
+        }
+    }
+}
+
 template <class T>
 static bool eigh_impl(int64_t p, const T *B, int64_t ldb, double *w, T *U, int64_t ldu) {
     if (p == 0) return true;
@@ -777,9 +829,13 @@ static bool eigh_impl(int64_t p, const T *B, int64_t ldb, double *w, T *U, int64
             for (int64_t b = (int64_t)blocks.size() - 1; b >= 0; --b) {
                 const ReflBlock<T> &rb = blocks[b];
                 const int64_t cnt = rb.cnt, r0 = rb.k0 + 1;
+                const bool tiled = std::is_same<T, double>::value && nc == kChunk && cnt % 4 == 0;
                 // W = Vb^H C[r0.., chunk]
-                std::fill(W.begin(), W.begin() + cnt * nc, T(0));
-                for (int64_t r = r0; r < p; ++r) {
+                if constexpr (std::is_same<T, double>::value) {
+                    if (tiled) refl_w_tiled(p - r0, cnt, rb.V.data(), C.row(r0) + j0, C.ld, W.data());
+                }
+                if (!tiled) std::fill(W.begin(), W.begin() + cnt * nc, T(0));
+                for (int64_t r = tiled ? p : r0; r < p; ++r) {
                     const T *cr = C.row(r) + j0;
                     const T *vr = &rb.V[(size_t)(r - r0) * cnt];
                     for (int64_t l = 0; l < cnt; ++l) {
@@ -799,7 +855,10 @@ static bool eigh_impl(int64_t p, const T *B, int64_t ldb, double *w, T *U, int64
                     }
                 }
                 // C -= Vb W2
-                for (int64_t r = r0; r < p; ++r) {
+                if constexpr (std::is_same<T, double>::value) {
+                    if (tiled) refl_update_tiled(p - r0, cnt, rb.V.data(), W2.data(), C.row(r0) + j0, C.ld);
+                }
+                for (int64_t r = tiled ? p : r0; r < p; ++r) {
                     T *cr = C.row(r) + j0;
                     const T *vr = &rb.V[(size_t)(r - r0) * cnt];
                     for (int64_t l = 0; l < cnt; ++l) {
