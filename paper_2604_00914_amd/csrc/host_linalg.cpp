@@ -21,6 +21,7 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <omp.h>
 #include <type_traits>
 #include <cstdlib>
 #include <new>
@@ -681,28 +682,27 @@ static bool eigh_impl(int64_t p, const T *B, int64_t ldb, double *w, T *U, int64
     // k+1..p-1, H_k = I - 2 v_k v_k^H) maps column k to (.., alpha_k, 0, ..).  With
     // u_k = A_k v_k (A_k the trailing matrix from k+1), gamma = v_k^H u_k and
     // w_k = 2 u_k - 2 gamma v_k, H_k A_k H_k = A_k - v_k w_k^H - w_k v_k^H.  Per column,
-    // one thread applies that update to column k+1 only and forms reflector k+1 from
-    // it; then the threads sweep the rows once, each row receiving update k and giving
-    // its entry of u_{k+1} = A_{k+1} v_{k+1}: two barriers per column and one pass over
-    // the trailing matrix.  Row k+1 is never read again and is left stale.
+    // every thread forms w_k, applies update k to column k+1 and forms reflector k+1
+    // from it, each in its own copy (O(p) work, the same arithmetic everywhere); then
+    // the threads sweep the rows once, each row receiving update k and giving its entry
+    // of u_{k+1} = A_{k+1} v_{k+1}: one barrier per column and one pass over the trailing
+    // matrix.  Only the diagonal of column k+1 is written back (the rest of that column
+    // is used by reflector k+1 alone); row k+1 is never read again and is left stale.
     std::vector<std::vector<T>> V(p);
-    std::vector<T> vb[2] = {std::vector<T>(p), std::vector<T>(p)};
+    std::vector<T> vb0(p);
     std::vector<T> ub[2] = {std::vector<T>(p), std::vector<T>(p)};
-    std::vector<T> wk(p), wkc(p);  // w_k and its conjugate
-    bool have[2] = {false, false};
-    // reflector from column k (rows k+1.., up to date); false if the column is reduced
-    auto make_reflector = [&](int64_t k, std::vector<T> &v, T &alpha) -> bool {
-        const int64_t m = p - k - 1;
+    // reflector from x[0..m) (the part of a column below the diagonal); false if x = 0
+    auto make_reflector = [](int64_t m, const T *x, std::vector<T> &v, T &alpha) -> bool {
         double xn2 = 0.0;
-        for (int64_t i = 0; i < m; ++i) xn2 += absq(A[(k + 1 + i) * p + k]);
+        for (int64_t i = 0; i < m; ++i) xn2 += absq(x[i]);
         const double xn = std::sqrt(xn2);
-        const T x0 = A[(k + 1) * p + k];
+        const T x0 = x[0];
         alpha = x0;
         if (xn == 0.0) return false;
         const double ax0 = std::sqrt(absq(x0));
         const T phase = ax0 > 0 ? x0 / ax0 : T(1);
         alpha = -phase * xn;
-        for (int64_t i = 0; i < m; ++i) v[i] = A[(k + 1 + i) * p + k];
+        for (int64_t i = 0; i < m; ++i) v[i] = x[i];
         v[0] -= alpha;
         double vn2 = 0.0;
         for (int64_t i = 0; i < m; ++i) vn2 += absq(v[i]);
@@ -714,36 +714,51 @@ static bool eigh_impl(int64_t p, const T *B, int64_t ldb, double *w, T *U, int64
     const bool householder_threads =
         p * (int64_t)(sizeof(T) / sizeof(double)) >= kHouseholderParallelMin;
     if (p > 2) {
-        have[0] = make_reflector(0, vb[0], alphas[0]);
+        std::vector<T> col0(p - 1);
+        for (int64_t i = 0; i + 1 < p; ++i) col0[i] = A[(1 + i) * p];
+        const bool have0 = make_reflector(p - 1, col0.data(), vb0, alphas[0]);
 #pragma omp parallel if (householder_threads)
         {
+            const bool lead = omp_get_thread_num() == 0;
+            std::vector<T> vp[2] = {vb0, std::vector<T>(p)};  // v_k, v_{k+1} (this thread's)
+            std::vector<T> wk(p), wkc(p), col(p);           // w_k, its conjugate, column k+1
+            bool have[2] = {have0, false};
             if (have[0]) {
 #pragma omp for schedule(static)
                 for (int64_t i = 0; i < p - 1; ++i)
-                    ub[0][i] = dot_lanes(&A[(1 + i) * p + 1], vb[0].data(), p - 1);
+                    ub[0][i] = dot_lanes(&A[(1 + i) * p + 1], vp[0].data(), p - 1);
             }
             for (int64_t k = 0; k + 2 < p; ++k) {
                 const int cur = (int)(k & 1), nxt = cur ^ 1;
-                const std::vector<T> &v = vb[cur];
-#pragma omp single
-                {
-                    const int64_t m = p - k - 1;
-                    if (have[cur]) {
-                        const std::vector<T> &u = ub[cur];
-                        T gamma = T(0);
-                        for (int64_t i = 0; i < m; ++i) gamma += conjv(v[i]) * u[i];
-                        const double g = realv(gamma);
-                        for (int64_t i = 0; i < m; ++i) {
-                            wk[i] = 2.0 * u[i] - 2.0 * g * v[i];
-                            wkc[i] = conjv(wk[i]);
-                        }
-                        // update k on column k+1 (rows k+1.., index i = row - (k+1))
-                        const T w0c = wkc[0], v0c = conjv(v[0]);
-                        for (int64_t i = 0; i < m; ++i) A[(k + 1 + i) * p + k + 1] -= v[i] * w0c + wk[i] * v0c;
-                        V[k].assign(v.begin(), v.begin() + m);
+                const std::vector<T> &v = vp[cur];
+                const int64_t m = p - k - 1;
+                // column k+1 from row k+1 down, with update k applied (index i = row - (k+1))
+                for (int64_t i = 0; i < m; ++i) col[i] = A[(k + 1 + i) * p + k + 1];
+                if (have[cur]) {
+                    const std::vector<T> &u = ub[cur];
+                    T gamma = T(0);
+                    for (int64_t i = 0; i < m; ++i) gamma += conjv(v[i]) * u[i];
+                    const double g = realv(gamma);
+                    for (int64_t i = 0; i < m; ++i) {
+                        wk[i] = 2.0 * u[i] - 2.0 * g * v[i];
+                        wkc[i] = conjv(wk[i]);
                     }
+                    const T w0c = wkc[0], v0c = conjv(v[0]);
+                    for (int64_t i = 0; i < m; ++i) col[i] -= v[i] * w0c + wk[i] * v0c;
+                }
+                T alpha_next = T(0);
+                have[nxt] = k + 3 < p && make_reflector(m - 1, col.data() + 1, vp[nxt], alpha_next);
+                if (lead) {
+                    A[(k + 1) * p + k + 1] = col[0];
+                    if (have[cur]) V[k].assign(v.begin(), v.begin() + m);
                     A[(k + 1) * p + k] = alphas[k];
-                    have[nxt] = k + 3 < p && make_reflector(k + 1, vb[nxt], alphas[k + 1]);
+                    // alpha_{k+1}: the subdiagonal entry of column k+1 once reflected, written
+                    // at the next column; the last column has no reflector and keeps its
+                    // updated subdiagonal entry
+                    if (k + 3 < p)
+                        alphas[k + 1] = alpha_next;
+                    else
+                        A[(k + 2) * p + k + 1] = col[1];
                 }
                 // rows k+2..: update k on columns k+2.., then u_{k+1} entries
                 const bool upd = have[cur], nx = have[nxt];
@@ -757,7 +772,7 @@ static bool eigh_impl(int64_t p, const T *B, int64_t ldb, double *w, T *U, int64
                         const T *vj = &v[1];
                         for (int64_t j = 0; j < m1; ++j) ar[j] -= vi * wcj[j] + wi * conjv(vj[j]);
                     }
-                    if (nx) ub[nxt][r - k - 2] = dot_lanes(ar, vb[nxt].data(), m1);
+                    if (nx) ub[nxt][r - k - 2] = dot_lanes(ar, vp[nxt].data(), m1);
                 }
             }
         }
