@@ -365,7 +365,11 @@ static bool dc_leaf(int64_t n, double *d, const double *e, double *Z, int64_t ld
 
 // Root j of the secular equation with poles p[0] < ... < p[k-1], weights w = rho z^2
 // (all > 0): the root is found as origin + tau, origin its nearer pole; returns false
-// if the iteration does not settle.
+// if the iteration does not settle.  Steps: the two-pole rational model of Li's
+// "middle way" (the poles left of the root summed as psi, those right as phi; each
+// replaced by a constant plus one pole term matching its value and slope at tau, and
+// the model's root taken), Newton where that model has no root between the poles, and
+// bisection of the bracket where a step leaves it.
 static bool secular_root(int64_t k, const double *p, const double *w, double rho, int64_t j,
                          double &origin, double &tau) {
     const double eps = std::numeric_limits<double>::epsilon();
@@ -390,16 +394,50 @@ static bool secular_root(int64_t k, const double *p, const double *w, double rho
     for (int64_t i = 0; i < k; ++i) off[i] = p[i] - origin;
     double t = 0.5 * (a + b);
     for (int it = 0; it < 400; ++it) {
-        double g = 1.0, gp = 0.0;
-        for (int64_t i = 0; i < k; ++i) {
+        double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0;
+        for (int64_t i = 0; i <= j; ++i) {
             const double q = 1.0 / (off[i] - t);
-            g += w[i] * q;
-            gp += w[i] * q * q;
+            psi += w[i] * q;
+            dpsi += w[i] * q * q;
         }
+        for (int64_t i = j + 1; i < k; ++i) {
+            const double q = 1.0 / (off[i] - t);
+            phi += w[i] * q;
+            dphi += w[i] * q * q;
+        }
+        const double g = 1.0 + psi + phi, gp = dpsi + dphi;
         if (g == 0.0) break;
         if (g < 0.0) a = t; else b = t;
         if (b - a <= 2.0 * eps * std::max(std::fabs(a), std::fabs(b))) break;
-        double tn = t - g / gp;  // Newton; bisect when it leaves the bracket
+        // two-pole model in the correction eta: c + B1 / (dl - eta) + B2 / (dr - eta) = 0
+        double tn = t - g / gp;
+        const double dl = off[j] - t;
+        const double B1 = dpsi * dl * dl;
+        double c = 1.0 + (psi - dpsi * dl), eta = 0.0;
+        bool ok = false;
+        if (j + 1 < k) {
+            const double dr = off[j + 1] - t;
+            const double B2 = dphi * dr * dr;
+            c += phi - dphi * dr;
+            // c eta^2 - (c (dl + dr) + B1 + B2) eta + (c dl dr + B1 dr + B2 dl) = 0,
+            // the root with dl < eta < dr
+            const double qa = c, qb = -(c * (dl + dr) + B1 + B2), qc = c * dl * dr + B1 * dr + B2 * dl;
+            if (qa == 0.0) {
+                if (qb != 0.0) { eta = -qc / qb; ok = true; }
+            } else {
+                const double disc = qb * qb - 4.0 * qa * qc;
+                if (disc >= 0.0) {
+                    const double qq = -0.5 * (qb + std::copysign(std::sqrt(disc), qb));
+                    const double r1 = qq / qa, r2 = qq != 0.0 ? qc / qq : r1;
+                    if (r1 > dl && r1 < dr) { eta = r1; ok = true; }
+                    else if (r2 > dl && r2 < dr) { eta = r2; ok = true; }
+                }
+            }
+        } else if (c != 0.0) {  // last root: no pole to the right, c (dl - eta) + B1 = 0
+            eta = dl + B1 / c;
+            ok = eta > dl;
+        }
+        if (ok) tn = t + eta;
         if (!(tn > a && tn < b)) tn = 0.5 * (a + b);
         if (tn == t) break;
         t = tn;
@@ -409,20 +447,54 @@ static bool secular_root(int64_t k, const double *p, const double *w, double rho
     return true;
 }
 
-// C (n x k, ldc) = A (n x k, lda) B (k x k, ldb), rows in parallel, four at a time.
+// C (n x k, ldc) = A (n x k, lda) B (k x k, ldb), rows in parallel, four at a time, each
+// four-row group in register tiles of eight columns; terms whose four A entries are all
+// zero (the block structure of diag(Q1, Q2)) are skipped.  Every C entry sums its terms
+// over l in order, as a plain loop would.
 static void dense_product(int64_t n, int64_t k, const double *A, int64_t lda, const double *B,
                           int64_t ldb, double *C, int64_t ldc) {
 #pragma omp parallel for schedule(static) if (n * k * k >= 4000000)
     for (int64_t i0 = 0; i0 < n; i0 += 4) {
         const int64_t rows = std::min<int64_t>(4, n - i0);
-        for (int64_t r = 0; r < rows; ++r) std::fill(C + (i0 + r) * ldc, C + (i0 + r) * ldc + k, 0.0);
-        for (int64_t l = 0; l < k; ++l) {
-            const double *b = B + l * ldb;
-            for (int64_t r = 0; r < rows; ++r) {
-                const double a = A[(i0 + r) * lda + l];
-                if (a == 0.0) continue;
-                double *c = C + (i0 + r) * ldc;
-                for (int64_t j = 0; j < k; ++j) c[j] += a * b[j];
+        if (rows < 4) {
+            for (int64_t r = 0; r < rows; ++r) std::fill(C + (i0 + r) * ldc, C + (i0 + r) * ldc + k, 0.0);
+            for (int64_t l = 0; l < k; ++l) {
+                const double *b = B + l * ldb;
+                for (int64_t r = 0; r < rows; ++r) {
+                    const double a = A[(i0 + r) * lda + l];
+                    if (a == 0.0) continue;
+                    double *c = C + (i0 + r) * ldc;
+                    for (int64_t j = 0; j < k; ++j) c[j] += a * b[j];
+                }
+            }
+            continue;
+        }
+        const double *a0 = A + i0 * lda;
+        int64_t jb = 0;
+        for (; jb + 8 <= k; jb += 8) {
+            double acc[4][8] = {};
+            for (int64_t l = 0; l < k; ++l) {
+                const double x0 = a0[l], x1 = a0[lda + l], x2 = a0[2 * lda + l], x3 = a0[3 * lda + l];
+                if (x0 == 0.0 && x1 == 0.0 && x2 == 0.0 && x3 == 0.0) continue;
+                const double *b = B + l * ldb + jb;
+                for (int j = 0; j < 8; ++j) {
+                    acc[0][j] += x0 * b[j];
+                    acc[1][j] += x1 * b[j];
+                    acc[2][j] += x2 * b[j];
+                    acc[3][j] += x3 * b[j];
+                }
+            }
+            for (int r = 0; r < 4; ++r)
+                for (int j = 0; j < 8; ++j) C[(i0 + r) * ldc + jb + j] = acc[r][j];
+        }
+        for (; jb < k; ++jb) {
+            for (int r = 0; r < 4; ++r) {
+                double acc = 0.0;
+                for (int64_t l = 0; l < k; ++l) {
+                    const double a = a0[r * lda + l];
+                    if (a != 0.0) acc += a * B[l * ldb + jb];
+                }
+                C[(i0 + r) * ldc + jb] = acc;
             }
         }
     }
