@@ -122,8 +122,8 @@ def main():
         cpu_sweep(args.cpu_baseline_sweep)   # host only: the oracle on every workload
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(see the sharding notes in DESIGN.md); use --gpus 1", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path; "
+              "use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
